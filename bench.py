@@ -1,0 +1,167 @@
+"""Throughput of the rollout planner on one MI355X.
+
+One step = one full planning call (Step 5 of Alg. 1, Sect. II-E) at the full-scale workload:
+N = 65536 parameter samples of an 8-32-32-2 tanh controller (1410 parameters), horizon T = 50,
+3000 obstacle points (2000 static + 20 moving obstacles x 50 points), every sample rolled over
+the whole horizon with the rectangle test against every point at every step, then the argmin
+and the winner's outputs. Ten synthetic scenes (seeds 0..9) stay resident in device memory and
+the steps cycle through them.
+
+Prints one JSON line: rollout-steps/s = N * T * steps / wall time of the timed steps, the
+rollout kernel's roofline figures (device time from HIP events recorded around that kernel on
+its stream), and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_SAMPLES, HORIZON, N_SCENES = 65536, 50, 10
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (vendor figure, packed FP32)
+FLOPS_PER_POINT_TEST = 11         # translate 2, rotate 6, squared distance 3
+FLOPS_STEP_OVERHEAD = 75          # features, control map, model, effort (transcendentals = 0)
+
+
+def mlp_flops(widths) -> int:
+    macs = sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1))
+    biases = sum(widths[1:])
+    return 2 * macs + biases
+
+
+def algorithmic_flops(N: int, T: int, P: int, widths) -> float:
+    """FP32 flops of one rollout launch: N * [(T+1) * P * 11 + T * (MLP + overhead)]."""
+    return float(N) * ((T + 1) * P * FLOPS_PER_POINT_TEST + T * (mlp_flops(widths)
+                                                                + FLOPS_STEP_OVERHEAD))
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("nnplan.hip", "rollout.hpp", "philox.hpp"):
+        with open(os.path.join(ROOT, "paper_1904_06680_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_hash: str):
+    """HBM bytes per rollout launch from the committed rocprofv3 counter summary, or None when
+    the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "rollout_c1_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, preset, target_s: float) -> dict:
+    import numpy as np
+
+    import oracle
+    m = oracle.make_model(preset)
+    ob = oracle.SceneBuf(scene.z0, scene.goal, scene.a_prev_or_idle(preset), scene.points,
+                         scene.T)
+    cal = 64
+    t0 = time.perf_counter()
+    oracle.rollout_samples(m, ob, 0, 0, np.arange(cal), want_traj=False, want_controls=False)
+    dt = time.perf_counter() - t0
+    n = int(min(N_SAMPLES, max(cal, cal * target_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.rollout_samples(m, ob, 0, 0, np.arange(n), want_traj=False, want_controls=False)
+    el = time.perf_counter() - t0
+    return {"value": n * scene.T / el, "unit": "rollout-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"samples 0..{n - 1} of scene 0 (full T={scene.T}, P={scene.P}), FP64, "
+                      f"{el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the planner's "
+              "multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1904_06680_amd import scenes
+    from paper_1904_06680_amd.nnplan import Planner
+
+    dev = torch.device("cuda", 0)
+    preset = scenes.C1
+    pl = Planner(preset, device=0)
+    scs = [scenes.scene_c1(s) for s in range(N_SCENES)]
+    probs = []
+    for sc in scs:
+        pr, keep = pl.problem(sc, N_SAMPLES, seed=0)
+        probs.append((pr, keep, pl.alloc_result(sc.T)))
+    P = scs[0].P
+    assert all(sc.P == P and sc.T == HORIZON for sc in scs)
+    stream = torch.cuda.current_stream(dev)
+
+    for k in range(args.warmup):
+        pr, _, out = probs[k % N_SCENES]
+        pl.plan_async(pr, out)
+    torch.cuda.synchronize(dev)
+
+    pl.set_timing(True)
+    pl.kernel_time(reset=True)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pr, _, out = probs[k % N_SCENES]
+        pl.plan_async(pr, out)
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t0
+    kern_ms, launches = pl.kernel_time(reset=True)
+    pl.set_timing(False)
+    costs = [float(probs[k][2]["cost"].item()) for k in range(min(N_SCENES, args.steps))]
+
+    value = N_SAMPLES * HORIZON * args.steps / elapsed
+    flops = algorithmic_flops(N_SAMPLES, HORIZON, P, preset["widths"])
+    avg_s = kern_ms / max(launches, 1) / 1e3
+    achieved = flops / avg_s / 1e12
+    khash = source_hash()
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": traffic_record(khash), "kernel": "rollout_kernel<8-32-32-2, K=4>",
+            "kernel_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops,
+            "source_hash": khash}
+    line = {
+        "metric": "rollout-steps/s (N=65536,T=50)",
+        "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain planner, full scale: N=65536 samples, T=50, MLP 8-32-32-2 "
+                               "(1410 params), 2000 static + 20x50 moving obstacle points, "
+                               "10 seeded scenes",
+                   "N": N_SAMPLES, "T": HORIZON, "P": P, "mlp": "8-32-32-2",
+                   "scenes": N_SCENES, "parallelism": "single GPU"},
+        "roofline": roof,
+        "best_costs_first_scenes": [round(c, 4) for c in costs[:3]],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(scs[0], preset, args.cpu_seconds)
+    pl.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,168 @@
+/*
+ * nnplan: MI355X (gfx950) batched closed-loop rollout planner.
+ *
+ * The method is the one of M. G. Plessen, "Online Sampling in the Parameter Space of a Neural
+ * Network for GPU-accelerated Motion Planning of Autonomous Vehicles": at every sampling time a
+ * population of neural-network parameter vectors theta is drawn, each theta is held constant and
+ * rolled over the prediction horizon in closed loop (features s_{t+h} of eq. (3), controls
+ * a_{t+h} = X(s_{t+h}, theta) of eq. (4), kinematic model of Sect. II-F), constant-velocity
+ * extrapolated obstacle points are tested against the vehicle rectangle with the linear
+ * inequalities of eq. (2) at every step, and the best parameter vector is returned (Step 5 of
+ * Alg. 1, Sect. II-E).
+ *
+ * Conventions for every entry point:
+ *  - All float arithmetic on the device is IEEE binary32.
+ *  - "device" pointers are HIP global-memory addresses on the handle's device; "host" pointers are
+ *    ordinary CPU memory that the call reads before returning. The library never frees or keeps
+ *    caller memory.
+ *  - hip_stream is a hipStream_t (NULL = the default stream). Device work is enqueued on it and
+ *    the call returns without waiting; device outputs are valid once the stream has been
+ *    synchronised. Calls on one handle must be ordered (one stream, or explicit events).
+ *  - Return values: NNP_OK on success, a negative NNP_E* code on failure (nothing is enqueued on
+ *    failure). nnp_last_error() gives a readable reason for the handle's last failure.
+ *  - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef NNPLAN_H
+#define NNPLAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NNP_OK 0
+#define NNP_INFEASIBLE 1      /* device status value: every sample collides                 */
+#define NNP_EINVAL (-1)       /* bad argument: null pointer, size out of range, non-finite   */
+#define NNP_ENOMEM (-2)       /* device allocation failed                                    */
+#define NNP_EDEVICE (-3)      /* a HIP call failed; see nnp_last_error()                     */
+#define NNP_EUNSUPPORTED (-4) /* network shape / lane layout without a compiled kernel       */
+
+#define NNP_MAX_LAYERS 3
+#define NNP_MAX_T 4096        /* longest horizon accepted                                    */
+#define NNP_MAX_P (1 << 22)   /* most obstacle points accepted                               */
+
+/* Feature vectors of eq. (3) (Sect. II-E) and the two extended variants:
+ * NNP_FEAT_PAPER  5 inputs: [xi_g/dxi, eta_g/deta, wrap(phi_g-phi)/dphi, (v_g-v)/dv, a_prev[0]]
+ * NNP_FEAT_SIX    6 inputs: [xi_g/dxi, eta_g/deta, wrap(phi_g-phi)/dphi, v/dv,
+ *                            min(d_near,d_cap)/d_cap, a_prev[0]]
+ * NNP_FEAT_EIGHT  8 inputs: the six, then [(v_g-v)/dv, a_prev[1]]
+ * (xi_g, eta_g) is the goal position in the vehicle frame of step h; d_near the distance from the
+ * reference point to the nearest extrapolated obstacle point at step h.                          */
+#define NNP_FEAT_PAPER 0
+#define NNP_FEAT_SIX 1
+#define NNP_FEAT_EIGHT 2
+
+/* Vehicle, controller and cost constants (Sect. II-F, Table I, Table II). Copied at creation. */
+typedef struct nnp_model {
+    float dt;                        /* sampling time T_s [s]                                   */
+    float lf, lr;                    /* reference point (CoG) to front / rear axle [m]          */
+    float front, rear, half_width;   /* rectangle extents from the reference point [m]: ahead,  */
+                                     /* behind, to each side                                    */
+    float delta_max;                 /* steering limit [rad]: delta = delta_max * a[0]          */
+    float delta_rate_max;            /* steering-rate limit [rad/s]; 0 disables it              */
+    float u_min, u_max;              /* acceleration range [m/s^2] mapped from a[1] in [-1, 1]   */
+    float v_min, v_max;              /* speed clamp after every step (+-INFINITY = none)        */
+    int32_t n_layers;                /* weight layers of the tanh MLP: 2 or 3                   */
+    int32_t widths[NNP_MAX_LAYERS + 1]; /* widths[0] = inputs, ..., widths[n_layers] = 2       */
+    int32_t feature_set;             /* NNP_FEAT_*; must match widths[0]                        */
+    float norm_xi, norm_eta, norm_phi, norm_v; /* Delta normalisers of eq. (3)                  */
+    float d_cap;                     /* cap of the nearest-obstacle distance feature [m]        */
+    float effort_weight;             /* cost = |p_T - g_xy| + effort_weight*T_s*sum|a_h|^2     */
+    float eps_xi, eps_eta, eps_phi, eps_v; /* goal tolerances for the goal_reached flag          */
+    int32_t lanes_per_sample;        /* 0 = library default for the network; else 1, 2, 4, 8    */
+} nnp_model;
+
+/* One planning problem at sampling time t (Sect. II-E, fourth comment: what is passed to the GPU
+ * every t: theta source (seed), m_t^z, a_{t-1}, zeta_t^goal, m_t^ext). */
+typedef struct nnp_problem {
+    float z0[4];              /* host copy: x, y, heading phi in [-pi, pi], speed v             */
+    float goal[4];            /* host copy: zeta^goal = x, y, phi in [-pi, pi], v (eq. (1))     */
+    const float *a_prev;      /* host [2] previous controls a_{t-1}; NULL = [0, a_idle]         */
+                              /* (zero acceleration, Sect. III)                                 */
+    const float *obst;        /* device [P][4] rows x, y, vx, vy of the obstacle points at t;   */
+                              /* may be NULL when P = 0                                         */
+    int32_t P;                /* number of obstacle points, 0..NNP_MAX_P                        */
+    int32_t N;                /* number of parameter samples, >= 1                              */
+    int32_t T;                /* horizon steps H, 1..NNP_MAX_T                                  */
+    uint32_t inst;            /* Philox instance word (fourth counter word)                     */
+    uint64_t seed;            /* Philox key                                                     */
+    const float *warm_theta;  /* device [n_theta] or NULL: replaces sample 0 (warm start of    */
+                              /* the first restart with theta*_{t-1}, Sect. II-E fifth comment) */
+} nnp_problem;
+
+/* Outputs of nnp_plan: caller-owned device buffers; any member may be NULL to skip it. */
+typedef struct nnp_result {
+    float *theta;             /* [n_theta] best parameter vector theta*                          */
+    float *controls;          /* [T][2] normalised controls a_h of theta* (after rate limit)     */
+    float *controls_phys;     /* [T][2] steering delta [rad], acceleration u [m/s^2]             */
+    float *traj;              /* [T+1][4] states z_h of theta*                                   */
+    float *cost;              /* [1] best cost (+INFINITY when infeasible)                       */
+    int32_t *best_index;      /* [1] sample index of theta* (lowest index among equal costs)     */
+    int32_t *status;          /* [1] NNP_OK, or NNP_INFEASIBLE when every sample collides (the   */
+                              /*     outputs then describe sample 0)                             */
+    int32_t *goal_reached;    /* [1] 1 if z_T is within the eps tolerances of the goal           */
+} nnp_result;
+
+/* Per-sample outputs of nnp_rollout: caller-owned device buffers; NULL skips a member. */
+typedef struct nnp_rollout_out {
+    float *cost;              /* [N] cost per sample, +INFINITY if it collides at some h in 0..T */
+    int32_t *collided;        /* [N] 0/1                                                         */
+    int32_t *first_collision; /* [N] first step h with a point inside, -1 if none               */
+    float *min_margin;        /* [N] min over h and points of max(|xi_c|/hl, |eta|/hw): < 1      */
+                              /*     exactly when some point is inside (diagnostic)              */
+    float *traj;              /* [N][T+1][4] states                                              */
+    float *controls;          /* [N][T][2] normalised controls                                   */
+} nnp_rollout_out;
+
+typedef struct nnp_handle nnp_handle;
+
+/* Create a planner for model *m on HIP device `device`. Validates the model (finite constants,
+ * positive extents, supported network shape, feature set consistent with widths[0]) and
+ * allocates the handle's small device workspace. Returns NNP_EINVAL / NNP_EUNSUPPORTED /
+ * NNP_ENOMEM / NNP_EDEVICE on failure, with *h set to NULL. */
+int nnp_create(nnp_handle **h, const nnp_model *m, int device);
+
+/* Release the handle and its workspace. NULL is accepted. Waits for the handle's device work. */
+void nnp_destroy(nnp_handle *h);
+
+/* Number of parameters of the handle's network (Table III counts: weights plus biases). */
+int nnp_n_theta(const nnp_handle *h);
+
+/* Step 5 of Alg. 1 as a plain sampler (Sect. II-E): draw N parameter vectors from Philox, roll
+ * each over h = 0..T with collision checks of eq. (2) at every h, cost every sample, and return
+ * the lowest-cost one (lowest index on ties) with its controls and trajectory. Every sample is
+ * simulated over the whole horizon. */
+int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
+
+/* Same rollout kernel as nnp_plan, with per-sample outputs instead of the argmin. theta, if not
+ * NULL, is a device [N][n_theta] array of parameters used instead of the Philox draws (explicit-
+ * parameter hook for tests and for externally proposed samples); p->warm_theta is ignored then. */
+int nnp_rollout(nnp_handle *h, const nnp_problem *p, const float *theta, nnp_rollout_out *o,
+                void *hip_stream);
+
+/* The parameter draws of nnp_plan for samples i0..i0+N-1 into device out[N][n_theta]:
+ * theta_k of sample i = (2m + 1 - 2^24) 2^-24, m the top 24 bits of word k mod 4 of
+ * Philox4x32-10(counter = (k / 4, i, 0, inst), key = (seed low 32, seed high 32)). Runs on the
+ * current HIP device. */
+int nnp_sample_theta(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
+                     float *out, void *hip_stream);
+
+/* Text of the handle's last error ("" if none). With h == NULL: the last nnp_create failure. */
+const char *nnp_last_error(const nnp_handle *h);
+
+/* Device-time instrumentation of the rollout kernel: when enabled, nnp_plan and nnp_rollout
+ * bracket the rollout-kernel launch with HIP events on the caller's stream. nnp_kernel_time
+ * synchronises on the last recorded event and returns the summed kernel milliseconds and the
+ * number of launches since the last reset. */
+int nnp_set_timing(nnp_handle *h, int enable);
+int nnp_kernel_time(nnp_handle *h, double *ms, int64_t *launches, int reset);
+
+/* Library version string. */
+const char *nnp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

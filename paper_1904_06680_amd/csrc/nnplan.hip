@@ -1,0 +1,707 @@
+// nnplan: kernels and C-ABI of the MI355X rollout planner (declarations in include/nnplan.h).
+//
+// One planning call (Step 5 of Alg. 1, Sect. II-E) is three launches on the caller's stream:
+//   1. extrapolate_kernel  obstacle points at every step h = 0..T under constant velocity
+//                          (Sect. II-E items (ii)-(iv)) into a [T+1][P16] table of (x, y); it
+//                          also resets the argmin key.
+//   2. rollout_kernel      every sample rolled over the horizon: Philox parameters in
+//                          registers, per step an LDS-staged pass over all points (eq. (2) and the
+//                          nearest distance), features (eq. (3)), MLP (eq. (4)), model (Sect. II-F)
+//                          and the cost; a u64 (cost bits, index) atomicMin selects the best
+//                          sample, lowest index on ties.
+//   3. replay_kernel       one workgroup re-simulates the winner with the same device functions
+//                          (points split over 256 lanes) and writes theta*, controls, trajectory.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nnplan.h"
+#include "philox.hpp"
+#include "rollout.hpp"
+
+using namespace nnp;
+
+namespace {
+
+constexpr int BLOCK = 256;
+constexpr int TILE_PAIRS = 1024;                // points per LDS tile = 2 * TILE_PAIRS
+constexpr int PREFETCH = TILE_PAIRS / BLOCK;    // float4 pairs staged per thread
+constexpr int POINT_PAD = 16;                   // points per step padded to a multiple of this
+
+struct RolloutArgs {
+    DevModel m;
+    float z0[4], goal[4], a_prev[2];
+    int N, T, P2, ntiles;            // P2 = padded points / 2 (float4 pairs per step)
+    const float4 *ext;               // [T+1][P2] extrapolated point pairs
+    PhiloxKey key;
+    uint32_t inst;
+    const float *theta;              // explicit [N][n_theta] or null
+    const float *warm_theta;         // replaces sample 0 when not null
+    unsigned long long *best_key;    // plan mode
+    float *cost;                     // rollout mode outputs (each may be null)
+    int32_t *collided, *first;
+    float *min_margin, *traj, *controls;
+};
+
+struct ReplayOut {
+    float *theta, *controls, *controls_phys, *traj, *cost;
+    int32_t *best_index, *status, *goal_reached;
+};
+
+enum { MODE_PLAN = 0, MODE_OUT = 1 };
+
+// ---------------------------------------------------------------------------------------------
+// 1. Constant-velocity extrapolation table; padding repeats the last point (min-neutral).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__restrict__ pts, int P,
+                                                            int P2, int T, float dt,
+                                                            float4 *__restrict__ ext,
+                                                            unsigned long long *best_key)
+{
+    const long long n = (long long)(T + 1) * P2;
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid == 0 && best_key) *best_key = ~0ull;
+    if (gid >= n || P == 0) return;
+    const int h = (int)(gid / P2);
+    const int j = (int)(gid % P2);
+    const float t = (float)h * dt;
+    const float4 a = pts[min(2 * j, P - 1)];
+    const float4 b = pts[min(2 * j + 1, P - 1)];
+    ext[gid] = make_float4(fmaf(t, a.z, a.x), fmaf(t, a.w, a.y), fmaf(t, b.z, b.x),
+                           fmaf(t, b.w, b.y));
+}
+
+template <class NetT>
+__device__ __forceinline__ ThetaSource make_source(const RolloutArgs &a, int sample)
+{
+    ThetaSource src;
+    src.key = a.key;
+    src.inst = a.inst;
+    src.sample = (uint32_t)sample;
+    src.explicit_theta = nullptr;
+    if (a.theta) src.explicit_theta = a.theta + (size_t)sample * NetT::NTHETA;
+    else if (a.warm_theta && sample == 0) src.explicit_theta = a.warm_theta;
+    return src;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float wave_min_f(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// 2. The rollout of every sample.
+// ---------------------------------------------------------------------------------------------
+template <class NetT, int K, int MODE>
+__global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
+{
+    __shared__ v4f tile[2][TILE_PAIRS];
+    const int tid = threadIdx.x;
+    const int q = (tid & 63) % K;
+    const int sample = (int)(((long long)blockIdx.x * BLOCK + tid) / K);
+    const bool active = sample < a.N;
+    const int si = active ? sample : a.N - 1;
+
+    SampleSim<NetT, K> sim;
+    sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&tile[0][0]), tid, BLOCK);
+    sim.init(a.z0, a.a_prev);
+    __syncthreads();
+
+    // The table holds TILE_PAIRS pairs of slack past its end, so whole tiles are always
+    // loaded; entries past a tile's count are never read.
+    const int P2 = a.P2, ntiles = a.ntiles;
+    const int total = (a.T + 1) * ntiles;
+    const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
+    v4f pf[PREFETCH];
+    if (total > 0) {
+#pragma unroll
+        for (int r = 0; r < PREFETCH; ++r) tile[0][tid + r * BLOCK] = ext[tid + r * BLOCK];
+    }
+    __syncthreads();
+
+    int it = 0;
+    for (int h = 0; h <= a.T; ++h) {
+        sim.begin_step(a.m);
+        float mm = INFINITY, md = INFINITY;
+        for (int t = 0; t < ntiles; ++t, ++it) {
+            const bool has_next = it + 1 < total;
+            int nh = h, nt = t + 1;
+            if (nt == ntiles) {
+                nt = 0;
+                ++nh;
+            }
+            const v4f *src = ext + (size_t)nh * P2 + (size_t)nt * TILE_PAIRS;
+            if (has_next) {
+#pragma unroll
+                for (int r = 0; r < PREFETCH; ++r) pf[r] = src[tid + r * BLOCK];
+            }
+            const int cnt = min(TILE_PAIRS, P2 - t * TILE_PAIRS);
+            const v4f *buf = tile[it & 1];
+#pragma unroll 4
+            for (int pi = q; pi < cnt; pi += K) sim.pair(buf[pi], mm, md);
+            if (has_next) {
+                v4f *dst = tile[(it + 1) & 1];
+#pragma unroll
+                for (int r = 0; r < PREFETCH; ++r) dst[tid + r * BLOCK] = pf[r];
+            }
+            __syncthreads();
+        }
+        mm = group_min<K>(mm);
+        md = group_min<K>(md);
+        sim.record_collision(h, mm);
+        if constexpr (MODE == MODE_OUT) {
+            if (a.traj && active && q == 0) {
+                float *o = a.traj + ((size_t)sample * (a.T + 1) + h) * 4;
+                *reinterpret_cast<float4 *>(o) = make_float4(sim.x, sim.y, sim.phi, sim.v);
+            }
+        }
+        if (h < a.T) {
+            float a0, a1;
+            sim.advance(a.m, a.goal, md, a0, a1);
+            if constexpr (MODE == MODE_OUT) {
+                if (a.controls && active && q == 0) {
+                    float *o = a.controls + ((size_t)sample * a.T + h) * 2;
+                    *reinterpret_cast<float2 *>(o) = make_float2(a0, a1);
+                }
+            }
+        }
+    }
+
+    const float J = sim.cost(a.m, a.goal);
+    if constexpr (MODE == MODE_PLAN) {
+        unsigned long long key = ~0ull;
+        if (active && q == 0)
+            key = ((unsigned long long)__float_as_uint(J) << 32) | (unsigned int)sample;
+        key = wave_min_u64(key);
+        if ((tid & 63) == 0 && key != ~0ull) atomicMin(a.best_key, key);
+    } else {
+        if (active && q == 0) {
+            if (a.cost) a.cost[sample] = J;
+            if (a.collided) a.collided[sample] = sim.first >= 0;
+            if (a.first) a.first[sample] = sim.first;
+            if (a.min_margin) a.min_margin[sample] = sim.min_margin;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// 3. Winner replay: every lane simulates the best sample; points are split over the workgroup
+//    and reduced exactly (min), so the replay reproduces the rollout bit for bit.
+// ---------------------------------------------------------------------------------------------
+template <class NetT, int K>
+__global__ __launch_bounds__(BLOCK) void replay_kernel(const RolloutArgs a, const ReplayOut o)
+{
+    __shared__ float red[2][BLOCK / 64];
+    __shared__ float stage[ThetaSource::STAGE * BLOCK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = lane % K;
+    const unsigned long long key = *a.best_key;
+    int best = (int)(unsigned int)(key & 0xffffffffull);
+    if (key == ~0ull || best >= a.N) best = 0;
+    const float key_cost = __uint_as_float((unsigned int)(key >> 32));
+
+    const ThetaSource src = make_source<NetT>(a, best);
+    SampleSim<NetT, K> sim;
+    sim.ctl.load(src, q, stage, tid, BLOCK);
+    sim.init(a.z0, a.a_prev);
+    for (int h = 0; h <= a.T; ++h) {
+        sim.begin_step(a.m);
+        float mm = INFINITY, md = INFINITY;
+        const v4f *pts = reinterpret_cast<const v4f *>(a.ext) + (size_t)h * a.P2;
+        if (a.ntiles > 0)
+            for (int pi = tid; pi < a.P2; pi += BLOCK) sim.pair(pts[pi], mm, md);
+        mm = wave_min_f(mm);
+        md = wave_min_f(md);
+        if (lane == 0) {
+            red[0][wave] = mm;
+            red[1][wave] = md;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            mm = fminf(mm, red[0][w]);
+            md = fminf(md, red[1][w]);
+        }
+        __syncthreads();
+        sim.record_collision(h, mm);
+        if (tid == 0 && o.traj)
+            *reinterpret_cast<float4 *>(o.traj + 4 * (size_t)h) =
+                make_float4(sim.x, sim.y, sim.phi, sim.v);
+        if (h < a.T) {
+            float a0, a1;
+            sim.advance(a.m, a.goal, md, a0, a1);
+            if (tid == 0) {
+                if (o.controls) {
+                    o.controls[2 * h] = a0;
+                    o.controls[2 * h + 1] = a1;
+                }
+                if (o.controls_phys) {
+                    o.controls_phys[2 * h] = a.m.delta_max * a0;
+                    o.controls_phys[2 * h + 1] = fmaf(a1 + 1.0f, a.m.u_half_range, a.m.u_min);
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        if (o.cost) o.cost[0] = sim.cost(a.m, a.goal);
+        if (o.best_index) o.best_index[0] = best;
+        if (o.status) o.status[0] = isinf(key_cost) ? NNP_INFEASIBLE : NNP_OK;
+        if (o.goal_reached) {
+            sim.begin_step(a.m);
+            o.goal_reached[0] = sim.goal_reached(a.m, a.goal);
+        }
+    }
+    if (o.theta)
+        for (int k = tid; k < NetT::NTHETA; k += BLOCK) o.theta[k] = src.one(k);
+}
+
+__global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,
+                                                      uint32_t N, uint32_t nt,
+                                                      float *__restrict__ out)
+{
+    const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (gid >= (long long)N * nt) return;
+    const uint32_t i = (uint32_t)(gid / nt), k = (uint32_t)(gid % nt);
+    ThetaSource src;
+    src.explicit_theta = nullptr;
+    src.key = key;
+    src.inst = inst;
+    src.sample = i0 + i;
+    out[gid] = src.one((int)k);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Dispatch table over the compiled network shapes and lane layouts.
+// ---------------------------------------------------------------------------------------------
+struct Variant {
+    int widths[NNP_MAX_LAYERS + 1];
+    int n_layers, feature_set, K, ntheta;
+    void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
+    void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
+};
+
+template <class NetT, int K>
+void launch_rollout_t(const RolloutArgs &a, int mode, dim3 grid, hipStream_t s)
+{
+    if (mode == MODE_PLAN)
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN>), grid, dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT>), grid, dim3(BLOCK), 0, s, a);
+}
+
+template <class NetT, int K>
+void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
+{
+    hipLaunchKernelGGL((replay_kernel<NetT, K>), dim3(1), dim3(BLOCK), 0, s, a, o);
+}
+
+#define NNP_VARIANT(NIN, H1, H2, FEAT, K)                                                         \
+    {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, K,                              \
+     Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, K>,                  \
+     launch_replay_t<Net<NIN, H1, H2, FEAT>, K>}
+
+const Variant kVariants[] = {
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // 8-32-32-2, 1410 parameters
+    NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 1),      // 6-16-2, 146 parameters
+    NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 2),
+    NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 4),
+    NNP_VARIANT(5, 2, 0, NNP_FEAT_PAPER, 1),     // NN-[5,2,2]
+    NNP_VARIANT(5, 10, 0, NNP_FEAT_PAPER, 1),    // NN-[5,10,2]
+    NNP_VARIANT(5, 10, 10, NNP_FEAT_PAPER, 1),   // NN-[5,10,10,2]
+};
+
+const Variant *find_variant(const nnp_model *m, int K)
+{
+    for (const Variant &v : kVariants) {
+        if (v.n_layers != m->n_layers || v.feature_set != m->feature_set) continue;
+        bool same = true;
+        for (int l = 0; l <= m->n_layers; ++l) same = same && v.widths[l] == m->widths[l];
+        if (!same) continue;
+        if (K == 0 || K == v.K) return &v;   // the first listed layout is the default
+    }
+    return nullptr;
+}
+
+thread_local std::string g_create_error;
+
+bool finite_f(float v) { return isfinite(v); }
+
+}  // namespace
+
+struct nnp_handle {
+    nnp_model model;
+    DevModel dm;
+    const Variant *var;
+    int device;
+    unsigned long long *d_key = nullptr;
+    float4 *d_ext = nullptr;
+    size_t ext_bytes = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    double acc_ms = 0.0;
+    int64_t launches = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(nnp_handle *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(nnp_handle *h, hipError_t e, const char *what)
+{
+    return fail(h, NNP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_model(const nnp_model *m, std::string &why)
+{
+    const float pos[] = {m->dt, m->front + m->rear, m->half_width, m->lf + m->lr, m->delta_max,
+                         m->norm_xi, m->norm_eta, m->norm_phi, m->norm_v, m->d_cap};
+    for (float f : pos)
+        if (!(f > 0.0f) || !finite_f(f)) {
+            why = "model constants dt, front+rear, half_width, lf+lr, delta_max, norms and d_cap "
+                  "must be finite and positive";
+            return NNP_EINVAL;
+        }
+    const float fin[] = {m->lf, m->lr, m->front, m->rear, m->delta_rate_max, m->u_min, m->u_max,
+                         m->effort_weight, m->eps_xi, m->eps_eta, m->eps_phi, m->eps_v};
+    for (float f : fin)
+        if (!finite_f(f)) {
+            why = "model constants must be finite";
+            return NNP_EINVAL;
+        }
+    if (m->lr < 0.0f || m->front + m->rear <= 0.0f || m->delta_rate_max < 0.0f ||
+        !(m->u_max >= m->u_min) || isnan(m->v_min) || isnan(m->v_max) || !(m->v_max >= m->v_min)) {
+        why = "inconsistent model bounds (lr >= 0, rate >= 0, u_min <= u_max, v_min <= v_max)";
+        return NNP_EINVAL;
+    }
+    if (m->n_layers < 2 || m->n_layers > NNP_MAX_LAYERS || m->widths[m->n_layers] != 2) {
+        why = "the MLP needs 2..3 weight layers and 2 outputs";
+        return NNP_EINVAL;
+    }
+    const int nin = m->feature_set == NNP_FEAT_PAPER ? 5 : m->feature_set == NNP_FEAT_SIX ? 6
+                                                   : m->feature_set == NNP_FEAT_EIGHT ? 8 : -1;
+    if (nin < 0 || m->widths[0] != nin) {
+        why = "feature_set does not match widths[0]";
+        return NNP_EINVAL;
+    }
+    const int K = m->lanes_per_sample;
+    if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8) {
+        why = "lanes_per_sample must be 0, 1, 2, 4 or 8";
+        return NNP_EINVAL;
+    }
+    if (!find_variant(m, K)) {
+        why = "no compiled kernel for this network shape and lane layout";
+        return NNP_EUNSUPPORTED;
+    }
+    return NNP_OK;
+}
+
+DevModel derive(const nnp_model *m)
+{
+    DevModel d;
+    const float L = m->lf + m->lr;
+    const float hl = 0.5f * (m->front + m->rear);
+    d.dt = m->dt;
+    d.lr_over_L = m->lr / L;
+    d.inv_L = 1.0f / L;
+    d.ihl = 1.0f / hl;
+    d.ihw = 1.0f / m->half_width;
+    d.oc = 0.5f * (m->front - m->rear);
+    d.delta_max = m->delta_max;
+    d.rate = m->delta_rate_max > 0.0f ? m->delta_rate_max * m->dt / m->delta_max : 0.0f;
+    d.u_min = m->u_min;
+    d.u_half_range = 0.5f * (m->u_max - m->u_min);
+    d.v_min = m->v_min;
+    d.v_max = m->v_max;
+    d.inv_nxi = 1.0f / m->norm_xi;
+    d.inv_neta = 1.0f / m->norm_eta;
+    d.inv_nphi = 1.0f / m->norm_phi;
+    d.inv_nv = 1.0f / m->norm_v;
+    d.d_cap = m->d_cap;
+    d.inv_dcap = 1.0f / m->d_cap;
+    d.effort_scale = m->effort_weight * m->dt;
+    d.eps_xi = m->eps_xi;
+    d.eps_eta = m->eps_eta;
+    d.eps_phi = m->eps_phi;
+    d.eps_v = m->eps_v;
+    return d;
+}
+
+int check_problem(nnp_handle *h, const nnp_problem *p)
+{
+    if (!p) return fail(h, NNP_EINVAL, "null problem");
+    if (p->N < 1) return fail(h, NNP_EINVAL, "N must be >= 1");
+    if (p->T < 1 || p->T > NNP_MAX_T) return fail(h, NNP_EINVAL, "T must be in [1, NNP_MAX_T]");
+    if (p->P < 0 || p->P > NNP_MAX_P) return fail(h, NNP_EINVAL, "P must be in [0, NNP_MAX_P]");
+    if (p->P > 0 && !p->obst) return fail(h, NNP_EINVAL, "obst is null with P > 0");
+    if ((long long)p->N * h->var->K >= (1ll << 31))
+        return fail(h, NNP_EINVAL, "N too large for one launch");
+    for (int i = 0; i < 4; ++i)
+        if (!finite_f(p->z0[i]) || !finite_f(p->goal[i]))
+            return fail(h, NNP_EINVAL, "z0 and goal must be finite");
+    if (fabsf(p->z0[2]) > PI_F || fabsf(p->goal[2]) > PI_F)
+        return fail(h, NNP_EINVAL, "headings must lie in [-pi, pi]");
+    if (p->a_prev)
+        for (int i = 0; i < 2; ++i)
+            if (!(fabsf(p->a_prev[i]) <= 1.0f))
+                return fail(h, NNP_EINVAL, "a_prev must be finite and in [-1, 1]");
+    return NNP_OK;
+}
+
+// Build the launch arguments and the extrapolation table for one problem.
+int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
+{
+    int rc = check_problem(h, p);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    memset(&a, 0, sizeof a);
+    a.m = h->dm;
+    for (int i = 0; i < 4; ++i) {
+        a.z0[i] = p->z0[i];
+        a.goal[i] = p->goal[i];
+    }
+    if (p->a_prev) {
+        a.a_prev[0] = p->a_prev[0];
+        a.a_prev[1] = p->a_prev[1];
+    } else {
+        a.a_prev[0] = 0.0f;
+        a.a_prev[1] = -1.0f - 2.0f * h->model.u_min / (h->model.u_max - h->model.u_min);
+        if (!(h->model.u_max > h->model.u_min)) a.a_prev[1] = 0.0f;
+    }
+    const int P16 = p->P > 0 ? (p->P + POINT_PAD - 1) / POINT_PAD * POINT_PAD : 0;
+    a.N = p->N;
+    a.T = p->T;
+    a.P2 = P16 / 2;
+    a.ntiles = (a.P2 + TILE_PAIRS - 1) / TILE_PAIRS;
+    a.key.k0 = (uint32_t)(p->seed & 0xffffffffull);
+    a.key.k1 = (uint32_t)(p->seed >> 32);
+    a.inst = p->inst;
+    a.warm_theta = p->warm_theta;
+    const size_t need = ((size_t)(p->T + 1) * a.P2 + TILE_PAIRS) * sizeof(float4);
+    if (need > h->ext_bytes) {
+        if (h->d_ext) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+            hipFree(h->d_ext);
+            h->d_ext = nullptr;
+            h->ext_bytes = 0;
+        }
+        e = hipMalloc(&h->d_ext, need);
+        if (e != hipSuccess) {
+            h->d_ext = nullptr;
+            return fail(h, NNP_ENOMEM, "hipMalloc of the extrapolation table failed");
+        }
+        h->ext_bytes = need;
+    }
+    a.ext = h->d_ext;
+    a.best_key = h->d_key;
+    const long long n = (long long)(p->T + 1) * a.P2;
+    const unsigned grid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
+    hipLaunchKernelGGL(extrapolate_kernel, dim3(grid), dim3(BLOCK), 0, s,
+                       reinterpret_cast<const float4 *>(p->obst), p->P, a.P2, p->T, h->dm.dt,
+                       h->d_ext, h->d_key);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "extrapolate_kernel launch");
+    return NNP_OK;
+}
+
+hipEvent_t pool_event(nnp_handle *h)
+{
+    if (!h->ev_pool.empty()) {
+        hipEvent_t ev = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    return ev;
+}
+
+int launch_rollout(nnp_handle *h, const RolloutArgs &a, int mode, hipStream_t s)
+{
+    const long long lanes = (long long)a.N * h->var->K;
+    const dim3 grid((unsigned)((lanes + BLOCK - 1) / BLOCK));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+        e0 = pool_event(h);
+        e1 = pool_event(h);
+        if (e0) hipEventRecord(e0, s);
+    }
+    h->var->launch_rollout(a, mode, grid, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "rollout_kernel launch");
+    if (h->timing && e0 && e1) {
+        hipEventRecord(e1, s);
+        h->pending.emplace_back(e0, e1);
+    }
+    return NNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nnp_version(void) { return "nnplan 0.1 (gfx950)"; }
+
+int nnp_create(nnp_handle **out, const nnp_model *m, int device)
+{
+    if (!out) return fail(nullptr, NNP_EINVAL, "null handle pointer");
+    *out = nullptr;
+    if (!m) return fail(nullptr, NNP_EINVAL, "null model");
+    std::string why;
+    const int rc = check_model(m, why);
+    if (rc) return fail(nullptr, rc, why);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(nullptr, NNP_EINVAL, "no such device");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    nnp_handle *h = new (std::nothrow) nnp_handle();
+    if (!h) return fail(nullptr, NNP_ENOMEM, "host allocation failed");
+    h->model = *m;
+    h->dm = derive(m);
+    h->var = find_variant(m, m->lanes_per_sample);
+    h->device = device;
+    e = hipMalloc(&h->d_key, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        delete h;
+        return fail(nullptr, NNP_ENOMEM, "hipMalloc of the argmin key failed");
+    }
+    *out = h;
+    return NNP_OK;
+}
+
+void nnp_destroy(nnp_handle *h)
+{
+    if (!h) return;
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    for (auto &pr : h->pending) {
+        hipEventDestroy(pr.first);
+        hipEventDestroy(pr.second);
+    }
+    for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
+    if (h->d_ext) hipFree(h->d_ext);
+    if (h->d_key) hipFree(h->d_key);
+    delete h;
+}
+
+int nnp_n_theta(const nnp_handle *h) { return h ? h->var->ntheta : NNP_EINVAL; }
+
+int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream)
+{
+    if (!h) return NNP_EINVAL;
+    if (!r) return fail(h, NNP_EINVAL, "null result");
+    hipStream_t s = (hipStream_t)hip_stream;
+    RolloutArgs a;
+    int rc = prepare(h, p, a, s);
+    if (rc) return rc;
+    rc = launch_rollout(h, a, MODE_PLAN, s);
+    if (rc) return rc;
+    ReplayOut o = {r->theta, r->controls, r->controls_phys, r->traj, r->cost, r->best_index,
+                   r->status, r->goal_reached};
+    h->var->launch_replay(a, o, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "replay_kernel launch");
+    h->err.clear();
+    return NNP_OK;
+}
+
+int nnp_rollout(nnp_handle *h, const nnp_problem *p, const float *theta, nnp_rollout_out *o,
+                void *hip_stream)
+{
+    if (!h) return NNP_EINVAL;
+    if (!o) return fail(h, NNP_EINVAL, "null output");
+    hipStream_t s = (hipStream_t)hip_stream;
+    RolloutArgs a;
+    int rc = prepare(h, p, a, s);
+    if (rc) return rc;
+    a.theta = theta;
+    if (theta) a.warm_theta = nullptr;
+    a.cost = o->cost;
+    a.collided = o->collided;
+    a.first = o->first_collision;
+    a.min_margin = o->min_margin;
+    a.traj = o->traj;
+    a.controls = o->controls;
+    rc = launch_rollout(h, a, MODE_OUT, s);
+    if (rc) return rc;
+    h->err.clear();
+    return NNP_OK;
+}
+
+int nnp_sample_theta(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
+                     float *out, void *hip_stream)
+{
+    if (!out || N == 0 || n_theta == 0) return NNP_EINVAL;
+    const long long n = (long long)N * n_theta;
+    if (n >= (1ll << 40)) return NNP_EINVAL;
+    PhiloxKey key = {(uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32)};
+    hipLaunchKernelGGL(theta_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       (hipStream_t)hip_stream, key, inst, i0, N, n_theta, out);
+    return hipGetLastError() == hipSuccess ? NNP_OK : NNP_EDEVICE;
+}
+
+const char *nnp_last_error(const nnp_handle *h)
+{
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int nnp_set_timing(nnp_handle *h, int enable)
+{
+    if (!h) return NNP_EINVAL;
+    h->timing = enable != 0;
+    return NNP_OK;
+}
+
+int nnp_kernel_time(nnp_handle *h, double *ms, int64_t *launches, int reset)
+{
+    if (!h) return NNP_EINVAL;
+    for (auto &pr : h->pending) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, pr.first, pr.second);
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventElapsedTime");
+        h->acc_ms += t;
+        h->launches += 1;
+        h->ev_pool.push_back(pr.first);
+        h->ev_pool.push_back(pr.second);
+    }
+    h->pending.clear();
+    if (ms) *ms = h->acc_ms;
+    if (launches) *launches = h->launches;
+    if (reset) {
+        h->acc_ms = 0.0;
+        h->launches = 0;
+    }
+    return NNP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,342 @@
+// Device side of one planner sample: controller weights in registers, the closed loop of
+// Sect. II-E (features eq. (3) -> MLP eq. (4) -> control map and kinematic model of Sect. II-F),
+// the per-point rectangle test of eq. (2) and the cost.
+//
+// Lane layout: a sample occupies K adjacent lanes of a wavefront (K in {1, 2, 4}). Each lane
+// holds H/K rows of every hidden layer plus one row of the output layer, so a 1410-parameter
+// 8-32-32-2 network fits in registers at K = 4. The K lanes split the obstacle points of every
+// step and keep identical copies of the state; hidden activations are all-gathered with DPP lane
+// broadcasts. Every dot product runs over its inputs in index order whatever K is, so results
+// are bit-identical for every K.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace nnp {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr float PI_F = 3.14159274101257324f;        // smallest float above pi
+constexpr float TWO_PI_HI = 6.28318548202514648f;   // float nearest 2 pi (above it)
+constexpr float TWO_PI_LO = -1.74845553e-7f;         // 2 pi - TWO_PI_HI
+
+// Constants derived from nnp_model on the host (Table I, Table II and the cost weights).
+struct DevModel {
+    float dt;
+    float lr_over_L, inv_L;            // l_r / (l_f + l_r), 1 / (l_f + l_r)
+    float ihl, ihw, oc;                // 1/half-length, 1/half-width, centre offset along xi
+    float delta_max, rate;             // rate: max |a0 - a0_prev| per step, 0 = off
+    float u_min, u_half_range;         // u = u_min + (a1 + 1) * u_half_range
+    float v_min, v_max;
+    float inv_nxi, inv_neta, inv_nphi, inv_nv;
+    float d_cap, inv_dcap;
+    float effort_scale;                // effort_weight * dt
+    float eps_xi, eps_eta, eps_phi, eps_v;
+};
+
+// MLP shape: NIN inputs, hidden widths H1 and H2 (H2 = 0: one hidden layer), 2 tanh outputs.
+// Parameters are stored layer by layer, W_l row-major [n_l][n_{l-1}] followed by b_l.
+template <int NIN_, int H1_, int H2_, int FEAT_>
+struct Net {
+    static constexpr int NIN = NIN_, H1 = H1_, H2 = H2_, FEAT = FEAT_;
+    static constexpr int HL = H2 ? H2 : H1;     // width feeding the output layer
+    static constexpr int OFF_W1 = 0;
+    static constexpr int OFF_B1 = H1 * NIN;
+    static constexpr int OFF_W2 = OFF_B1 + H1;
+    static constexpr int OFF_B2 = OFF_W2 + H2 * H1;
+    static constexpr int OFF_WO = H2 ? OFF_B2 + H2 : OFF_W2;
+    static constexpr int OFF_BO = OFF_WO + 2 * HL;
+    static constexpr int NTHETA = OFF_BO + 2;
+};
+
+// ---------------------------------------------------------------------------------------------
+// Lane exchanges within a sample's K lanes (DPP quad permutations; K <= 4 stays in a quad).
+// ---------------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int K>
+__device__ __forceinline__ float group_min(float v)
+{
+    if constexpr (K >= 2) v = fminf(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
+    if constexpr (K >= 4) v = fminf(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
+    return v;
+}
+
+// Value of sub-lane B of the caller's group.
+template <int K, int B>
+__device__ __forceinline__ float group_bcast(float v)
+{
+    if constexpr (K == 1) return v;
+    else if constexpr (K == 2) return dpp_f<(B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6))>(v);
+    else return dpp_f<(B * 0x55)>(v);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Controller a = X(s, theta), eq. (4): tanh MLP, weights resident in registers.
+// ---------------------------------------------------------------------------------------------
+template <class NetT, int K>
+struct Controller {
+    static constexpr int NIN = NetT::NIN, H1 = NetT::H1, H2 = NetT::H2, HL = NetT::HL;
+    static constexpr int U1 = H1 / K;
+    static constexpr int U2 = H2 ? H2 / K : 1;
+    static constexpr int NO = K == 1 ? 2 : 1;       // output rows held by this lane
+    static_assert(H1 % K == 0 && (H2 == 0 || H2 % K == 0), "hidden widths must split over K");
+    static_assert(K == 1 || ((U1 * NIN) % 4 == 0 && NetT::OFF_B1 % 4 == 0 && U1 % 4 == 0 &&
+                             NetT::OFF_WO % 4 == 0 && HL % 4 == 0 &&
+                             (H2 == 0 || ((U2 * H1) % 4 == 0 && NetT::OFF_W2 % 4 == 0 &&
+                                          NetT::OFF_B2 % 4 == 0 && U2 % 4 == 0))),
+                  "parameter slices of a lane must start on Philox blocks");
+
+    float w1[U1 * NIN], b1[U1];
+    float w2[H2 ? U2 * H1 : 1], b2[U2];
+    float wo[NO * HL], bo[NO];
+
+    // stage: LDS scratch of ThetaSource::STAGE * block floats shared by the workgroup, each
+    // lane using its own column.
+    __device__ __forceinline__ void load(const ThetaSource &src, int q, float *stage, int tid,
+                                         int block)
+    {
+        if constexpr (K == 1) {
+            src.template fill_const<NetT::OFF_W1, U1 * NIN>(w1);
+            src.template fill_const<NetT::OFF_B1, U1>(b1);
+            if constexpr (H2) {
+                src.template fill_const<NetT::OFF_W2, U2 * H1>(w2);
+                src.template fill_const<NetT::OFF_B2, U2>(b2);
+            }
+            src.template fill_const<NetT::OFF_WO, NO * HL>(wo);
+            src.template fill_const<NetT::OFF_BO, NO>(bo);
+        } else {
+            src.fill_aligned(w1, NetT::OFF_W1 + q * U1 * NIN, stage, tid, block);
+            src.fill_aligned(b1, NetT::OFF_B1 + q * U1, stage, tid, block);
+            if constexpr (H2) {
+                src.fill_aligned(w2, NetT::OFF_W2 + q * U2 * H1, stage, tid, block);
+                src.fill_aligned(b2, NetT::OFF_B2 + q * U2, stage, tid, block);
+            }
+            const int r = q & 1;
+            src.fill_aligned(wo, NetT::OFF_WO + r * HL, stage, tid, block);
+            bo[0] = src.one(NetT::OFF_BO + r);
+        }
+    }
+
+    template <int U, int W>
+    __device__ __forceinline__ static void gather(const float (&own)[U], float (&full)[W])
+    {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            full[0 * U + u] = group_bcast<K, 0>(own[u]);
+            if constexpr (K >= 2) full[1 * U + u] = group_bcast<K, 1>(own[u]);
+            if constexpr (K >= 4) {
+                full[2 * U + u] = group_bcast<K, 2>(own[u]);
+                full[3 * U + u] = group_bcast<K, 3>(own[u]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void forward(const float (&s)[NIN], float &a0, float &a1) const
+    {
+        float h1o[U1];
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+            float acc = b1[u];
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) acc = fmaf(w1[u * NIN + i], s[i], acc);
+            h1o[u] = tanhf(acc);
+        }
+        float h1[H1];
+        gather(h1o, h1);
+        float hl[HL];
+        if constexpr (H2) {
+            float h2o[U2];
+#pragma unroll
+            for (int o = 0; o < U2; ++o) {
+                float acc = b2[o];
+#pragma unroll
+                for (int i = 0; i < H1; ++i) acc = fmaf(w2[o * H1 + i], h1[i], acc);
+                h2o[o] = tanhf(acc);
+            }
+            gather(h2o, hl);
+        } else {
+#pragma unroll
+            for (int i = 0; i < HL; ++i) hl[i] = h1[i];
+        }
+        float out[NO];
+#pragma unroll
+        for (int r = 0; r < NO; ++r) {
+            float acc = bo[r];
+#pragma unroll
+            for (int i = 0; i < HL; ++i) acc = fmaf(wo[r * HL + i], hl[i], acc);
+            out[r] = tanhf(acc);
+        }
+        if constexpr (K == 1) {
+            a0 = out[0];
+            a1 = out[1];
+        } else {
+            a0 = dpp_f<0xA0>(out[0]);   // quad_perm [0,0,2,2]: even lane of the pair
+            a1 = dpp_f<0xF5>(out[0]);   // quad_perm [1,1,3,3]: odd lane of the pair
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// One sample's closed-loop state.
+// ---------------------------------------------------------------------------------------------
+template <class NetT, int K>
+struct SampleSim {
+    Controller<NetT, K> ctl;
+    float x, y, phi, v;       // z_h
+    float ap0, ap1;           // a_{h-1}
+    float effort;             // sum of |a|^2 so far
+    float min_margin;         // min over steps and points of the normalised margin
+    int first;                // first step with a point inside, -1 if none
+    float c, s;               // cos / sin of phi at the current step
+    float cxi, sxi, oxi;      // xi' = (c dx + s dy - oc) / hl  = cxi dx + sxi dy + oxi
+    float ceta, seta;         // eta' = (c dy - s dx) / hw     = ceta dy - seta dx
+
+    __device__ __forceinline__ void init(const float (&z0)[4], const float (&a_prev)[2])
+    {
+        x = z0[0];
+        y = z0[1];
+        phi = z0[2];
+        v = z0[3];
+        ap0 = a_prev[0];
+        ap1 = a_prev[1];
+        effort = 0.0f;
+        min_margin = INFINITY;
+        first = -1;
+    }
+
+    // Pose-dependent constants of the obstacle pass at step h.
+    __device__ __forceinline__ void begin_step(const DevModel &m)
+    {
+        float sv, cv;
+        sincosf(phi, &sv, &cv);
+        s = sv;
+        c = cv;
+        cxi = c * m.ihl;
+        sxi = s * m.ihl;
+        oxi = -m.oc * m.ihl;
+        ceta = c * m.ihw;
+        seta = s * m.ihw;
+    }
+
+    // Eq. (2) for one extrapolated point, folded into the running minima of the normalised
+    // margin max(|xi'|, |eta'|) (< 1 exactly when the point is strictly inside) and of the
+    // squared distance to the reference point. Translate first, then rotate: dx, dy are exact
+    // for points near the vehicle, which keeps the test accurate near the faces.
+    __device__ __forceinline__ void point(float px, float py, float &mg, float &d2) const
+    {
+        const float dx = px - x, dy = py - y;
+        const float xi = fmaf(cxi, dx, fmaf(sxi, dy, oxi));
+        const float et = fmaf(ceta, dy, -(seta * dx));
+        mg = fmaxf(fabsf(xi), fabsf(et));
+        d2 = fmaf(dx, dx, dy * dy);
+    }
+
+    __device__ __forceinline__ void pair(v4f p, float &mm, float &md) const
+    {
+        float m0, d0, m1, d1;
+        point(p.x, p.y, m0, d0);
+        point(p.z, p.w, m1, d1);
+        mm = fminf(mm, fminf(m0, m1));
+        md = fminf(md, fminf(d0, d1));
+    }
+
+    // Collision bookkeeping of step h from the step's minima over all points.
+    __device__ __forceinline__ void record_collision(int h, float mm)
+    {
+        if (mm < 1.0f && first < 0) first = h;
+        min_margin = fminf(min_margin, mm);
+    }
+
+    // Features s_h of eq. (3) and its variants.
+    __device__ __forceinline__ void features(const DevModel &m, const float (&goal)[4], float md,
+                                             float (&f)[NetT::NIN]) const
+    {
+        const float gx = goal[0] - x, gy = goal[1] - y;
+        const float xi_g = fmaf(c, gx, s * gy);
+        const float eta_g = fmaf(c, gy, -(s * gx));
+        float dphi = goal[2] - phi;
+        if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
+        else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+        if constexpr (NetT::FEAT == 0) {
+            f[0] = xi_g * m.inv_nxi;
+            f[1] = eta_g * m.inv_neta;
+            f[2] = dphi * m.inv_nphi;
+            f[3] = (goal[3] - v) * m.inv_nv;
+            f[4] = ap0;
+        } else {
+            const float dn = fminf(sqrtf(md), m.d_cap);
+            f[0] = xi_g * m.inv_nxi;
+            f[1] = eta_g * m.inv_neta;
+            f[2] = dphi * m.inv_nphi;
+            f[3] = v * m.inv_nv;
+            f[4] = dn * m.inv_dcap;
+            f[5] = ap0;
+            if constexpr (NetT::FEAT == 2) {
+                f[6] = (goal[3] - v) * m.inv_nv;
+                f[7] = ap1;
+            }
+        }
+    }
+
+    // Controller, rate limit, control map, one explicit Euler step of the kinematic model.
+    // cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
+    // tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
+    __device__ __forceinline__ void advance(const DevModel &m, const float (&goal)[4], float md,
+                                            float &a0, float &a1)
+    {
+        float f[NetT::NIN];
+        features(m, goal, md, f);
+        ctl.forward(f, a0, a1);
+        if (m.rate > 0.0f) a0 = fminf(fmaxf(a0, ap0 - m.rate), ap0 + m.rate);
+        const float delta = m.delta_max * a0;
+        const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
+        const float td = tanf(delta);
+        const float tb = m.lr_over_L * td;
+        const float ds = m.dt * v;
+        const float nx = fmaf(ds, fmaf(-s, tb, c), x);
+        const float ny = fmaf(ds, fmaf(c, tb, s), y);
+        float nphi = fmaf(ds * td, m.inv_L, phi);
+        if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
+        else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
+        const float nv = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
+        effort = effort + fmaf(a0, a0, a1 * a1);
+        x = nx;
+        y = ny;
+        phi = nphi;
+        v = nv;
+        ap0 = a0;
+        ap1 = a1;
+    }
+
+    __device__ __forceinline__ float cost(const DevModel &m, const float (&goal)[4]) const
+    {
+        const float gx = x - goal[0], gy = y - goal[1];
+        float J = sqrtf(fmaf(gx, gx, gy * gy)) + m.effort_scale * effort;
+        if (first >= 0 || J != J) J = INFINITY;
+        return J;
+    }
+
+    // Tolerance test of Table II at the current state.
+    __device__ __forceinline__ int goal_reached(const DevModel &m, const float (&goal)[4]) const
+    {
+        const float gx = goal[0] - x, gy = goal[1] - y;
+        const float xi_g = fmaf(c, gx, s * gy);
+        const float eta_g = fmaf(c, gy, -(s * gx));
+        float dphi = goal[2] - phi;
+        if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
+        else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+        return fabsf(xi_g) <= m.eps_xi && fabsf(eta_g) <= m.eps_eta && fabsf(dphi) <= m.eps_phi &&
+               fabsf(goal[3] - v) <= m.eps_v;
+    }
+};
+
+}  // namespace nnp

@@ -1,0 +1,165 @@
+"""GPU-vs-oracle parity rules for planner rollouts.
+
+The GPU computes in binary32, the oracle in binary64, and the closed loop feeds rounding back
+through the controller, so the comparison is made sample by sample as follows.
+
+1. Conditioning. The oracle also runs each sample with its state rounded to float after every
+   step. A sample is well conditioned when that run stays within a tenth of the tolerances below
+   of the binary64 run; trajectories, controls and costs are compared only for well-conditioned
+   samples (the excluded count is reported and bounded by the caller).
+2. Trajectories (up to the oracle's first collision step): per component
+   |gpu - ref| <= 1e-4 * max(|ref|, 1) (x, y in m, v in m/s); headings are compared modulo
+   2 pi with an absolute 1e-4 rad. Controls: |gpu - ref| <= 1e-4.
+3. Collision flags: eq. (2) is re-evaluated in binary64 at the GPU's own poses for every step.
+   Points within 1e-5 m of a face (in the max-distance sense) make a step undecidable; the GPU's
+   first collision step must equal the first step with a point clearly inside unless an
+   undecidable step comes first.
+4. Costs: +inf must match +inf; finite costs agree within 1e-5 * max(cost, 1). A collision
+   status that differs between the GPU and the binary64 run is accepted only when the binary64
+   run passes a point closer to a face than the pose drift between the two trajectories.
+5. Argmin: if the oracle's best and second-best costs differ by more than 1e-5 * max(best, 1)
+   the indices must be equal, otherwise the GPU's pick must lie in that tie band.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+
+TRAJ_RTOL = 1e-4
+CTRL_ATOL = 1e-4
+COST_RTOL = 1e-5
+FACE_EPS = 1e-5
+TWO_PI = 2.0 * math.pi
+
+
+def oracle_scene(preset, scene):
+    return oracle.make_model(preset), oracle.SceneBuf(scene.z0, scene.goal,
+                                                      scene.a_prev_or_idle(preset), scene.points,
+                                                      scene.T)
+
+
+def _traj_err(a, b):
+    """Normalised per-step error of trajectories a (test) vs b (reference), shape [..., T+1]."""
+    ex = np.abs(a[..., 0] - b[..., 0]) / np.maximum(np.abs(b[..., 0]), 1.0)
+    ey = np.abs(a[..., 1] - b[..., 1]) / np.maximum(np.abs(b[..., 1]), 1.0)
+    dphi = np.abs((a[..., 2] - b[..., 2] + math.pi) % TWO_PI - math.pi)
+    ev = np.abs(a[..., 3] - b[..., 3]) / np.maximum(np.abs(b[..., 3]), 1.0)
+    return np.maximum(np.maximum(ex, ey), np.maximum(dphi, ev))
+
+
+def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
+                  theta_rows=None) -> dict:
+    """Compare the GPU rollout outputs (numpy arrays indexed by sample) for the sample indices
+    idx with the oracle. theta_rows: explicit parameters [len(idx)][n_theta] if the GPU ran with
+    explicit theta (None: Philox draws). Returns counts; raises AssertionError with details."""
+    idx = np.asarray(idx, dtype=np.int64)
+    m, ob = oracle_scene(preset, scene)
+    T = scene.T
+    if theta_rows is None:
+        ref = oracle.rollout_samples(m, ob, seed, inst, idx)
+        r32 = oracle.rollout_samples(m, ob, seed, inst, idx, fp32_state=True)
+    else:
+        ref = _rollout_rows(m, ob, theta_rows, False)
+        r32 = _rollout_rows(m, ob, theta_rows, True)
+    g_traj = gpu["traj"][idx].astype(np.float64)
+    g_ctrl = gpu["controls"][idx].astype(np.float64)
+    g_cost = gpu["cost"][idx].astype(np.float64)
+    g_first = gpu["first_collision"][idx]
+
+    # 3. flags at the GPU's poses
+    poses = g_traj[:, :, :3].reshape(-1, 3)
+    steps = np.tile(np.arange(T + 1), len(idx))
+    fl = oracle.flags_at_poses(m, ob, poses, steps, FACE_EPS).reshape(len(idx), T + 1)
+    undecided = 0
+    bad_flags = []
+    for r in range(len(idx)):
+        f = fl[r]
+        hits = np.flatnonzero(f == 1)
+        exp_first = int(hits[0]) if len(hits) else -1
+        upto = exp_first if exp_first >= 0 else T + 1
+        if np.any(f[:upto] == 2):
+            undecided += 1
+            continue
+        if g_first[r] != exp_first:
+            bad_flags.append((int(idx[r]), int(g_first[r]), exp_first))
+    assert not bad_flags, f"collision step mismatch (sample, gpu, oracle@gpu-poses): {bad_flags[:10]}"
+
+    # 1. conditioning
+    first64 = ref["first_collision"]
+    n_ill = 0
+    well = np.zeros(len(idx), bool)
+    for r in range(len(idx)):
+        upto = (first64[r] if first64[r] >= 0 else T) + 1
+        e32 = _traj_err(r32["traj"][r, :upto], ref["traj"][r, :upto]).max()
+        c64, c32 = ref["cost"][r], r32["cost"][r]
+        if math.isinf(c64) != math.isinf(c32):
+            cbad = True
+        else:
+            cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.1 * COST_RTOL * max(c64, 1.0)
+        well[r] = e32 <= 0.1 * TRAJ_RTOL and not cbad
+        n_ill += not well[r]
+
+    # 2. trajectories and controls, 4. costs
+    bad_traj, bad_cost, face_sensitive = [], [], 0
+    for r in np.flatnonzero(well):
+        upto = (first64[r] if first64[r] >= 0 else T) + 1
+        e = _traj_err(g_traj[r, :upto], ref["traj"][r, :upto])
+        if e.max() > TRAJ_RTOL:
+            bad_traj.append((int(idx[r]), float(e.max()), int(e.argmax())))
+            continue
+        nctl = min(upto, T)
+        ec = np.abs(g_ctrl[r, :nctl] - ref["controls"][r, :nctl]).max() if nctl else 0.0
+        if ec > CTRL_ATOL:
+            bad_traj.append((int(idx[r]), float(ec), -1))
+            continue
+        c64, cg = ref["cost"][r], g_cost[r]
+        if math.isinf(c64) and math.isinf(cg):
+            continue
+        if math.isinf(c64) != math.isinf(cg):
+            drift = np.abs(g_traj[r, :, :2] - ref["traj"][r, :, :2]).max()
+            if ref["min_abs_face"][r] <= 2 * drift + FACE_EPS:
+                face_sensitive += 1
+                continue
+            bad_cost.append((int(idx[r]), cg, c64))
+            continue
+        if abs(cg - c64) > COST_RTOL * max(c64, 1.0):
+            bad_cost.append((int(idx[r]), cg, c64))
+    assert not bad_traj, f"trajectory/control mismatch (sample, err, step): {bad_traj[:10]}"
+    assert not bad_cost, f"cost mismatch (sample, gpu, oracle): {bad_cost[:10]}"
+    return dict(n=len(idx), ill_conditioned=n_ill, undecided=undecided,
+                face_sensitive=face_sensitive, collided=int((first64 >= 0).sum()))
+
+
+def _rollout_rows(m, ob, rows, fp32_state):
+    T = ob.s.T
+    n = len(rows)
+    out = dict(traj=np.empty((n, T + 1, 4)), controls=np.empty((n, T, 2)), cost=np.empty(n),
+               first_collision=np.empty(n, np.int64), min_abs_face=np.empty(n))
+    for r in range(n):
+        rec = oracle.rollout(m, ob, np.asarray(rows[r], np.float64), fp32_state)
+        out["traj"][r] = rec["traj"]
+        out["controls"][r] = rec["controls"]
+        out["cost"][r] = rec["cost"]
+        out["first_collision"][r] = rec["first_collision"]
+        out["min_abs_face"][r] = rec["min_abs_face"]
+    return out
+
+
+def check_argmin(ref_cost, gpu_best: int):
+    """Rule 5 for a full oracle cost vector."""
+    c = np.asarray(ref_cost, np.float64)
+    order = np.argsort(c, kind="stable")
+    c0 = c[order[0]]
+    if math.isinf(c0):
+        assert gpu_best == 0, gpu_best
+        return "infeasible"
+    c1 = c[order[1]] if len(c) > 1 else math.inf
+    band = COST_RTOL * max(c0, 1.0)
+    if c1 - c0 > band:
+        assert gpu_best == int(order[0]), (gpu_best, int(order[0]), c0, c1)
+        return "exact"
+    assert c[gpu_best] <= c0 + band, (gpu_best, c[gpu_best], c0)
+    return "tie-band"

@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports what include/nnplan.h declares; host-side validation
+(no GPU needed: every case here is rejected before any HIP call)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_1904_06680_amd import nnplan, scenes
+
+HEADER = os.path.join(ROOT, "include", "nnplan.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nnp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(nnplan.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nnplan.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert nnplan.nnp_version().startswith("nnplan")
+
+
+def test_struct_layouts_match_header_sizes():
+    # Field-by-field mirror of the header structs; sizes follow the C layout rules.
+    assert C.sizeof(nnplan.nnp_model) == 4 * 12 + 4 + 16 + 4 + 4 * 6 + 4 * 4 + 4
+    assert C.sizeof(nnplan.nnp_problem) == 16 + 16 + 8 + 8 + 4 * 4 + 8 + 8
+    assert C.sizeof(nnplan.nnp_result) == 8 * 8
+    assert C.sizeof(nnplan.nnp_rollout_out) == 8 * 6
+
+
+def _create(preset, **over):
+    m = nnplan.make_model(preset)
+    for k, v in over.items():
+        if k == "widths":
+            for i in range(4):
+                m.widths[i] = v[i] if i < len(v) else 0
+            m.n_layers = len(v) - 1
+        else:
+            setattr(m, k, v)
+    return nnplan.nnp_create(m, 0)
+
+
+@pytest.mark.parametrize("over, code", [
+    (dict(dt=0.0), nnplan.NNP_EINVAL),
+    (dict(dt=math.nan), nnplan.NNP_EINVAL),
+    (dict(half_width=-1.0), nnplan.NNP_EINVAL),
+    (dict(u_min=3.0, u_max=-3.0), nnplan.NNP_EINVAL),
+    (dict(v_min=1.0, v_max=-1.0), nnplan.NNP_EINVAL),
+    (dict(feature_set=nnplan.FEAT_SIX), nnplan.NNP_EINVAL),            # 8 inputs, 6 features
+    (dict(widths=(8, 32, 32, 3)), nnplan.NNP_EINVAL),                  # 3 outputs
+    (dict(widths=(8, 64, 2)), nnplan.NNP_EUNSUPPORTED),                # no compiled kernel
+    (dict(lanes_per_sample=3), nnplan.NNP_EINVAL),
+    (dict(lanes_per_sample=1), nnplan.NNP_EUNSUPPORTED),               # 1410 weights per lane
+])
+def test_invalid_models_are_rejected_before_device_work(over, code):
+    rc, h = _create(scenes.C1, **over)
+    assert rc == code and not h.value
+    assert nnplan.nnp_last_error(None) != ""
+
+
+def test_null_arguments():
+    lib = nnplan.load_library()
+    assert lib.nnp_create(None, None, 0) == nnplan.NNP_EINVAL
+    h = C.c_void_p()
+    assert lib.nnp_create(C.byref(h), None, 0) == nnplan.NNP_EINVAL
+    assert lib.nnp_plan(None, None, None, None) == nnplan.NNP_EINVAL
+    assert lib.nnp_rollout(None, None, None, None, None) == nnplan.NNP_EINVAL
+    assert lib.nnp_sample_theta(0, 0, 0, 0, 10, None, None) == nnplan.NNP_EINVAL
+    assert lib.nnp_n_theta(None) == nnplan.NNP_EINVAL
+    lib.nnp_destroy(None)
