@@ -94,6 +94,7 @@ def lib():
             "orc_argmin": (I, [PD, I, PI]),
             "orc_plan": (I, [PM, PS, I, U64, U32, PD, PI, PD, PD, PD, PI]),
             "orc_flags_at_poses": (None, [PM, PD, I, D, PD, PI, I, D, PI]),
+            "orc_step_at_states": (None, [PM, PS, PD, PD, PD, PI, I, PD, PD, PD]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -219,7 +220,7 @@ def wrap_angle(a: float) -> float:
     return lib().orc_wrap_angle(float(a))
 
 
-def rollout(m: Model, sc: SceneBuf, th, fp32_state: bool = False) -> dict:
+def rollout(m: Model, sc: SceneBuf, th, fp32_state: int = 0) -> dict:
     T = sc.s.T
     traj = np.empty((T + 1, 4), np.float64)
     ctrl = np.empty((T, 2), np.float64)
@@ -234,7 +235,7 @@ def rollout(m: Model, sc: SceneBuf, th, fp32_state: bool = False) -> dict:
                 goal_reached=r.goal_reached)
 
 
-def rollout_samples(m: Model, sc: SceneBuf, seed: int, inst: int, idx, fp32_state=False,
+def rollout_samples(m: Model, sc: SceneBuf, seed: int, inst: int, idx, fp32_state=0,
                     want_traj=True, want_controls=True, want_dnear=False) -> dict:
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint32))
     n, T = len(idx), sc.s.T
@@ -283,6 +284,19 @@ def flags_at_poses(m: Model, sc: SceneBuf, poses, steps, eps: float) -> np.ndarr
     lib().orc_flags_at_poses(C.byref(m), sc.s.points if sc.s.P else None, sc.s.P, m.dt,
                              _pd(poses), _pi(steps), len(poses), float(eps), _pi(out))
     return out
+
+
+def step_at_states(m: Model, sc: SceneBuf, th, states, a_prev, steps) -> dict:
+    states = f64(states).reshape(-1, 4)
+    a_prev = f64(a_prev).reshape(-1, 2)
+    steps = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+    M = len(states)
+    a = np.empty((M, 2), np.float64)
+    zn = np.empty((M, 4), np.float64)
+    dn = np.empty(M, np.float64)
+    lib().orc_step_at_states(C.byref(m), C.byref(sc.s), _pd(f64(th)), _pd(states), _pd(a_prev),
+                             _pi(steps), M, _pd(a), _pd(zn), _pd(dn))
+    return dict(a=a, z_next=zn, d_near=dn)
 
 
 def num_threads() -> int:

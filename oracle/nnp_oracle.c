@@ -278,8 +278,9 @@ static int goal_reached(const orc_model *m, const double z[4], const double goal
 /* closed loop runs for h = 0..H, collision is checked at every h including h = 0 (eq. (2)), and */
 /* the cost is the terminal distance to the goal position plus effort_weight * T_s * sum |a|^2, */
 /* +inf on any collision.                                                                        */
-/* fp32_state rounds the state to float after every step; the tests use the gap between the two */
-/* runs to recognise samples whose outcome is ill-conditioned at float precision.                */
+/* fp32_state = 1 rounds the state to float after every step; 2 also rounds the features and the */
+/* applied controls. The tests use the gap to the plain run to recognise samples whose outcome is */
+/* ill-conditioned at float precision.                                                           */
 /* ------------------------------------------------------------------------------------------ */
 void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, int fp32_state,
                  orc_record *rec)
@@ -323,8 +324,14 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
 
         double s[ORC_MAX_WIDTH], a_raw[2], a[2], delta, u, zn[4];
         orc_features(m, z, sc->goal, d_near, ap, s);
+        if (fp32_state == 2)
+            for (int i = 0; i < m->widths[0]; ++i) s[i] = (double)(float)s[i];
         orc_mlp(m, theta, s, a_raw);
         orc_limit_rate(m, a_raw, ap, a);
+        if (fp32_state == 2) {
+            a[0] = (double)(float)a[0];
+            a[1] = (double)(float)a[1];
+        }
         orc_control_map(m, a, &delta, &u);
         orc_vehicle_step(m, z, delta, u, zn);
         effort += a[0] * a[0] + a[1] * a[1];
@@ -441,5 +448,39 @@ void orc_flags_at_poses(const orc_model *m, const double *points, int P, double 
             if (fabs(fd) <= eps) f = 2;
         }
         flag[i] = f;
+    }
+}
+
+/* One closed-loop step evaluated at given states: for each (z_h, a_{h-1}, h) the nearest
+ * extrapolated obstacle distance, the features, the controller, the rate limit and the model
+ * step, exactly as inside orc_rollout. Used to check a float implementation step by step at its
+ * own states, apart from the drift its rounding builds up over a whole horizon. */
+void orc_step_at_states(const orc_model *m, const orc_scene *sc, const double *theta,
+                        const double *states, const double *a_prev, const int *steps, int M,
+                        double *a_out, double *z_next, double *d_near)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int i = 0; i < M; ++i) {
+        const double *z = states + 4 * (size_t)i;
+        const double *ap = a_prev + 2 * (size_t)i;
+        double t = (double)steps[i] * m->dt;
+        double d2min = INFINITY;
+        for (int j = 0; j < sc->P; ++j) {
+            double p[2];
+            orc_extrapolate(sc->points + 4 * (size_t)j, t, p);
+            double dx = p[0] - z[0], dy = p[1] - z[1];
+            double d2 = dx * dx + dy * dy;
+            if (d2 < d2min) d2min = d2;
+        }
+        double dn = sqrt(d2min);
+        double s[ORC_MAX_WIDTH], a_raw[2], a[2], delta, u;
+        orc_features(m, z, sc->goal, dn, ap, s);
+        orc_mlp(m, theta, s, a_raw);
+        orc_limit_rate(m, a_raw, ap, a);
+        orc_control_map(m, a, &delta, &u);
+        orc_vehicle_step(m, z, delta, u, z_next + 4 * (size_t)i);
+        a_out[2 * (size_t)i] = a[0];
+        a_out[2 * (size_t)i + 1] = a[1];
+        if (d_near) d_near[i] = dn;
     }
 }

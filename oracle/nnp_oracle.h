@@ -100,6 +100,9 @@ int    orc_argmin(const double *cost, int n, int *best);
 int    orc_plan(const orc_model *m, const orc_scene *sc, int N, uint64_t seed, uint32_t inst,
                 double *cost, int *best, double *theta_best, double *traj_best,
                 double *controls_best, int *goal_reached);
+void   orc_step_at_states(const orc_model *m, const orc_scene *sc, const double *theta,
+                          const double *states, const double *a_prev, const int *steps, int M,
+                          double *a_out, double *z_next, double *d_near);
 void   orc_flags_at_poses(const orc_model *m, const double *points, int P, double dt,
                           const double *poses, const int *steps, int M, double eps, int *flag);
 

@@ -5,10 +5,10 @@
 //                          (Sect. II-E items (ii)-(iv)) into a [T+1][P16] table of (x, y); it
 //                          also resets the argmin key.
 //   2. rollout_kernel      every sample rolled over the horizon: Philox parameters in
-//                          registers, per step an LDS-staged pass over all points (eq. (2) and the
-//                          nearest distance), features (eq. (3)), MLP (eq. (4)), model (Sect. II-F)
-//                          and the cost; a u64 (cost bits, index) atomicMin selects the best
-//                          sample, lowest index on ties.
+//                          registers, per step a pass over all points (eq. (2) and the nearest
+//                          distance) fed by scalar loads, features (eq. (3)), MLP (eq. (4)),
+//                          model (Sect. II-F) and the cost; a u64 (cost bits, index) atomicMin
+//                          selects the best sample, lowest index on ties.
 //   3. replay_kernel       one workgroup re-simulates the winner with the same device functions
 //                          (points split over 256 lanes) and writes theta*, controls, trajectory.
 #include <hip/hip_runtime.h>
@@ -30,14 +30,13 @@ using namespace nnp;
 namespace {
 
 constexpr int BLOCK = 256;
-constexpr int TILE_PAIRS = 1024;                // points per LDS tile = 2 * TILE_PAIRS
-constexpr int PREFETCH = TILE_PAIRS / BLOCK;    // float4 pairs staged per thread
-constexpr int POINT_PAD = 16;                   // points per step padded to a multiple of this
+constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this (pairs per
+                                // subset then come in whole groups of eight for K <= 4)
 
 struct RolloutArgs {
     DevModel m;
     float z0[4], goal[4], a_prev[2];
-    int N, T, P2, ntiles;            // P2 = padded points / 2 (float4 pairs per step)
+    int N, T, P2;                    // P2 = padded points / 2 (float4 pairs per step)
     const float4 *ext;               // [T+1][P2] extrapolated point pairs
     PhiloxKey key;
     uint32_t inst;
@@ -107,65 +106,120 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
+// The obstacle pass of one lane: n consecutive point pairs p[0..n) (n a multiple of 8) against
+// one pose. p is the same for the whole wavefront, so the pairs arrive through scalar loads and
+// enter the arithmetic as scalar operands; no LDS traffic and no per-lane loads.
+typedef const __attribute__((address_space(4))) v4f const_v4f;   // read-only for the kernel
+
+__device__ __forceinline__ void point_pass(const Pose &pose, const const_v4f *p, int n, float &mm,
+                                           float &md)
+{
+    // Two register groups of four pairs alternate: one is loaded while the other is tested, so
+    // the scalar loads (L2 latency on their first touch) overlap the arithmetic. Scalar loads
+    // complete out of order and can only be waited for all together, so each group is waited
+    // for (the empty asm statements that read it) before the other group's load is issued.
+    // The scheduling barriers keep the compiler from moving loads next to their uses.
+    v4f a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
+    for (int i = 0; i < n; i += 8) {
+        asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3));
+        const v4f b0 = p[i + 4], b1 = p[i + 5], b2 = p[i + 6], b3 = p[i + 7];
+        __builtin_amdgcn_sched_barrier(0);
+        pose.pair(a0, mm, md);
+        pose.pair(a1, mm, md);
+        pose.pair(a2, mm, md);
+        pose.pair(a3, mm, md);
+        __builtin_amdgcn_sched_barrier(0);
+        asm volatile("" ::"s"(b0), "s"(b1), "s"(b2), "s"(b3));
+        const int na = i + 8 < n ? i + 8 : i;
+        a0 = p[na];
+        a1 = p[na + 1];
+        a2 = p[na + 2];
+        a3 = p[na + 3];
+        __builtin_amdgcn_sched_barrier(0);
+        pose.pair(b0, mm, md);
+        pose.pair(b1, mm, md);
+        pose.pair(b2, mm, md);
+        pose.pair(b3, mm, md);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // 2. The rollout of every sample.
+//
+// A workgroup holds S = BLOCK / K samples. For the controller a sample occupies K adjacent lanes
+// (its weights are split over them); for the obstacle pass every lane takes one sample and one
+// K-th of the points: lane t tests sample t % S against point subset t / S, which is the same
+// for the whole wavefront. Poses go out and per-subset minima come back through LDS, two
+// workgroup barriers per step (none when K = 1, where both layouts coincide).
 // ---------------------------------------------------------------------------------------------
 template <class NetT, int K, int MODE>
 __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
 {
-    __shared__ v4f tile[2][TILE_PAIRS];
+    constexpr int S = BLOCK / K;
+    static_assert(S % 64 == 0, "point subsets must be wavefront-uniform");
+    __shared__ float lds[ThetaSource::STAGE * BLOCK];   // weight staging, then pose exchange
+    float *pose_x = lds, *pose_y = lds + S, *pose_cxi = lds + 2 * S, *pose_sxi = lds + 3 * S;
+    float *pose_ceta = lds + 4 * S, *pose_seta = lds + 5 * S;
+    float *part_m = lds + 6 * S, *part_d = lds + 6 * S + BLOCK;
+
     const int tid = threadIdx.x;
     const int q = (tid & 63) % K;
-    const int sample = (int)(((long long)blockIdx.x * BLOCK + tid) / K);
+    const int slot = tid / K;                                  // controller layout
+    const int sample = blockIdx.x * S + slot;
     const bool active = sample < a.N;
     const int si = active ? sample : a.N - 1;
+    const int pslot = tid % S;                                 // obstacle-pass layout
+    const int psub = __builtin_amdgcn_readfirstlane(tid / S);
 
     SampleSim<NetT, K> sim;
-    sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&tile[0][0]), tid, BLOCK);
+    sim.ctl.load(make_source<NetT>(a, si), q, lds, tid, BLOCK);
     sim.init(a.z0, a.a_prev);
     __syncthreads();
 
-    // The table holds TILE_PAIRS pairs of slack past its end, so whole tiles are always
-    // loaded; entries past a tile's count are never read.
-    const int P2 = a.P2, ntiles = a.ntiles;
-    const int total = (a.T + 1) * ntiles;
+    const int P2 = a.P2;
+    const int n_sub = P2 / K;                                  // pairs per subset, multiple of 8
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
-    v4f pf[PREFETCH];
-    if (total > 0) {
-#pragma unroll
-        for (int r = 0; r < PREFETCH; ++r) tile[0][tid + r * BLOCK] = ext[tid + r * BLOCK];
-    }
-    __syncthreads();
+    const float oxi = -a.m.oc * a.m.ihl;
 
-    int it = 0;
     for (int h = 0; h <= a.T; ++h) {
-        sim.begin_step(a.m);
+        const Pose own = sim.begin_step(a.m);
         float mm = INFINITY, md = INFINITY;
-        for (int t = 0; t < ntiles; ++t, ++it) {
-            const bool has_next = it + 1 < total;
-            int nh = h, nt = t + 1;
-            if (nt == ntiles) {
-                nt = 0;
-                ++nh;
+        if (P2 > 0) {
+            Pose pose = own;
+            if constexpr (K > 1) {
+                if (q == 0) {
+                    pose_x[slot] = own.x;
+                    pose_y[slot] = own.y;
+                    pose_cxi[slot] = own.cxi;
+                    pose_sxi[slot] = own.sxi;
+                    pose_ceta[slot] = own.ceta;
+                    pose_seta[slot] = own.seta;
+                }
+                __syncthreads();
+                pose.x = pose_x[pslot];
+                pose.y = pose_y[pslot];
+                pose.cxi = pose_cxi[pslot];
+                pose.sxi = pose_sxi[pslot];
+                pose.oxi = oxi;
+                pose.ceta = pose_ceta[pslot];
+                pose.seta = pose_seta[pslot];
             }
-            const v4f *src = ext + (size_t)nh * P2 + (size_t)nt * TILE_PAIRS;
-            if (has_next) {
+            const const_v4f *pts = (const const_v4f *)(ext + (size_t)h * P2 + (size_t)psub * n_sub);
+            point_pass(pose, pts, n_sub, mm, md);
+            if constexpr (K > 1) {
+                part_m[tid] = mm;
+                part_d[tid] = md;
+                __syncthreads();
+                mm = part_m[slot];
+                md = part_d[slot];
 #pragma unroll
-                for (int r = 0; r < PREFETCH; ++r) pf[r] = src[tid + r * BLOCK];
+                for (int r = 1; r < K; ++r) {
+                    mm = fminf(mm, part_m[r * S + slot]);
+                    md = fminf(md, part_d[r * S + slot]);
+                }
             }
-            const int cnt = min(TILE_PAIRS, P2 - t * TILE_PAIRS);
-            const v4f *buf = tile[it & 1];
-#pragma unroll 4
-            for (int pi = q; pi < cnt; pi += K) sim.pair(buf[pi], mm, md);
-            if (has_next) {
-                v4f *dst = tile[(it + 1) & 1];
-#pragma unroll
-                for (int r = 0; r < PREFETCH; ++r) dst[tid + r * BLOCK] = pf[r];
-            }
-            __syncthreads();
         }
-        mm = group_min<K>(mm);
-        md = group_min<K>(md);
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
             if (a.traj && active && q == 0) {
@@ -223,11 +277,10 @@ __global__ __launch_bounds__(BLOCK) void replay_kernel(const RolloutArgs a, cons
     sim.ctl.load(src, q, stage, tid, BLOCK);
     sim.init(a.z0, a.a_prev);
     for (int h = 0; h <= a.T; ++h) {
-        sim.begin_step(a.m);
+        const Pose pose = sim.begin_step(a.m);
         float mm = INFINITY, md = INFINITY;
         const v4f *pts = reinterpret_cast<const v4f *>(a.ext) + (size_t)h * a.P2;
-        if (a.ntiles > 0)
-            for (int pi = tid; pi < a.P2; pi += BLOCK) sim.pair(pts[pi], mm, md);
+        for (int pi = tid; pi < a.P2; pi += BLOCK) pose.pair(pts[pi], mm, md);
         mm = wave_min_f(mm);
         md = wave_min_f(md);
         if (lane == 0) {
@@ -497,12 +550,11 @@ int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
     a.N = p->N;
     a.T = p->T;
     a.P2 = P16 / 2;
-    a.ntiles = (a.P2 + TILE_PAIRS - 1) / TILE_PAIRS;
     a.key.k0 = (uint32_t)(p->seed & 0xffffffffull);
     a.key.k1 = (uint32_t)(p->seed >> 32);
     a.inst = p->inst;
     a.warm_theta = p->warm_theta;
-    const size_t need = ((size_t)(p->T + 1) * a.P2 + TILE_PAIRS) * sizeof(float4);
+    const size_t need = (size_t)(p->T + 1) * a.P2 * sizeof(float4);
     if (need > h->ext_bytes) {
         if (h->d_ext) {
             e = hipStreamSynchronize(s);

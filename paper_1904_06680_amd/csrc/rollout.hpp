@@ -188,44 +188,12 @@ struct Controller {
 // ---------------------------------------------------------------------------------------------
 // One sample's closed-loop state.
 // ---------------------------------------------------------------------------------------------
-template <class NetT, int K>
-struct SampleSim {
-    Controller<NetT, K> ctl;
-    float x, y, phi, v;       // z_h
-    float ap0, ap1;           // a_{h-1}
-    float effort;             // sum of |a|^2 so far
-    float min_margin;         // min over steps and points of the normalised margin
-    int first;                // first step with a point inside, -1 if none
-    float c, s;               // cos / sin of phi at the current step
+// The vehicle pose at one step in the form the obstacle pass consumes.
+// ---------------------------------------------------------------------------------------------
+struct Pose {
+    float x, y;
     float cxi, sxi, oxi;      // xi' = (c dx + s dy - oc) / hl  = cxi dx + sxi dy + oxi
     float ceta, seta;         // eta' = (c dy - s dx) / hw     = ceta dy - seta dx
-
-    __device__ __forceinline__ void init(const float (&z0)[4], const float (&a_prev)[2])
-    {
-        x = z0[0];
-        y = z0[1];
-        phi = z0[2];
-        v = z0[3];
-        ap0 = a_prev[0];
-        ap1 = a_prev[1];
-        effort = 0.0f;
-        min_margin = INFINITY;
-        first = -1;
-    }
-
-    // Pose-dependent constants of the obstacle pass at step h.
-    __device__ __forceinline__ void begin_step(const DevModel &m)
-    {
-        float sv, cv;
-        sincosf(phi, &sv, &cv);
-        s = sv;
-        c = cv;
-        cxi = c * m.ihl;
-        sxi = s * m.ihl;
-        oxi = -m.oc * m.ihl;
-        ceta = c * m.ihw;
-        seta = s * m.ihw;
-    }
 
     // Eq. (2) for one extrapolated point, folded into the running minima of the normalised
     // margin max(|xi'|, |eta'|) (< 1 exactly when the point is strictly inside) and of the
@@ -247,6 +215,51 @@ struct SampleSim {
         point(p.z, p.w, m1, d1);
         mm = fminf(mm, fminf(m0, m1));
         md = fminf(md, fminf(d0, d1));
+    }
+};
+
+// ---------------------------------------------------------------------------------------------
+// One sample's closed-loop state.
+// ---------------------------------------------------------------------------------------------
+template <class NetT, int K>
+struct SampleSim {
+    Controller<NetT, K> ctl;
+    float x, y, phi, v;       // z_h
+    float ap0, ap1;           // a_{h-1}
+    float effort;             // sum of |a|^2 so far
+    float min_margin;         // min over steps and points of the normalised margin
+    int first;                // first step with a point inside, -1 if none
+    float c, s;               // cos / sin of phi at the current step
+
+    __device__ __forceinline__ void init(const float (&z0)[4], const float (&a_prev)[2])
+    {
+        x = z0[0];
+        y = z0[1];
+        phi = z0[2];
+        v = z0[3];
+        ap0 = a_prev[0];
+        ap1 = a_prev[1];
+        effort = 0.0f;
+        min_margin = INFINITY;
+        first = -1;
+    }
+
+    // Heading of step h and the pose constants of its obstacle pass.
+    __device__ __forceinline__ Pose begin_step(const DevModel &m)
+    {
+        float sv, cv;
+        sincosf(phi, &sv, &cv);
+        s = sv;
+        c = cv;
+        Pose p;
+        p.x = x;
+        p.y = y;
+        p.cxi = c * m.ihl;
+        p.sxi = s * m.ihl;
+        p.oxi = -m.oc * m.ihl;
+        p.ceta = c * m.ihw;
+        p.seta = s * m.ihw;
+        return p;
     }
 
     // Collision bookkeeping of step h from the step's minima over all points.

@@ -3,13 +3,20 @@
 The GPU computes in binary32, the oracle in binary64, and the closed loop feeds rounding back
 through the controller, so the comparison is made sample by sample as follows.
 
-1. Conditioning. The oracle also runs each sample with its state rounded to float after every
-   step. A sample is well conditioned when that run stays within a tenth of the tolerances below
-   of the binary64 run; trajectories, controls and costs are compared only for well-conditioned
-   samples (the excluded count is reported and bounded by the caller).
+1. Conditioning. The oracle also runs each sample twice more with float rounding injected: the
+   state rounded after every step, and in addition the features and the applied controls. A
+   sample is well conditioned when both runs stay within a tenth of the tolerances below of the
+   binary64 run; closed-loop trajectories and costs are compared only for well-conditioned
+   samples (the excluded count is reported and bounded by the caller). Every sample, well
+   conditioned or not, goes through the step-by-step check 2b and the flag check 3.
 2. Trajectories (up to the oracle's first collision step): per component
    |gpu - ref| <= 1e-4 * max(|ref|, 1) (x, y in m, v in m/s); headings are compared modulo
-   2 pi with an absolute 1e-4 rad. Controls: |gpu - ref| <= 1e-4.
+   2 pi with an absolute 1e-4 rad.
+2b. Step by step at the GPU's own states (every sample, every step): the oracle recomputes the
+   nearest distance, features, controller output and model step from the GPU's float state
+   z_h and previous controls. Controls must agree within 2e-5 (measured worst case 3e-6: the
+   controller's gain times the float rounding of its inputs and dot products), the next state
+   within 1e-6 * max(|z|, 1) (measured worst case 6e-7).
 3. Collision flags: eq. (2) is re-evaluated in binary64 at the GPU's own poses for every step.
    Points within 1e-5 m of a face (in the max-distance sense) make a step undecidable; the GPU's
    first collision step must equal the first step with a point clearly inside unless an
@@ -29,7 +36,8 @@ import numpy as np
 import oracle
 
 TRAJ_RTOL = 1e-4
-CTRL_ATOL = 1e-4
+CTRL_STEP_ATOL = 2e-5
+MODEL_STEP_RTOL = 1e-6
 COST_RTOL = 1e-5
 FACE_EPS = 1e-5
 TWO_PI = 2.0 * math.pi
@@ -60,10 +68,11 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
     T = scene.T
     if theta_rows is None:
         ref = oracle.rollout_samples(m, ob, seed, inst, idx)
-        r32 = oracle.rollout_samples(m, ob, seed, inst, idx, fp32_state=True)
+        perturbed = [oracle.rollout_samples(m, ob, seed, inst, idx, fp32_state=mode)
+                     for mode in (1, 2)]
     else:
-        ref = _rollout_rows(m, ob, theta_rows, False)
-        r32 = _rollout_rows(m, ob, theta_rows, True)
+        ref = _rollout_rows(m, ob, theta_rows, 0)
+        perturbed = [_rollout_rows(m, ob, theta_rows, mode) for mode in (1, 2)]
     g_traj = gpu["traj"][idx].astype(np.float64)
     g_ctrl = gpu["controls"][idx].astype(np.float64)
     g_cost = gpu["cost"][idx].astype(np.float64)
@@ -87,33 +96,51 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
             bad_flags.append((int(idx[r]), int(g_first[r]), exp_first))
     assert not bad_flags, f"collision step mismatch (sample, gpu, oracle@gpu-poses): {bad_flags[:10]}"
 
+    # 2b. one step at the GPU's own states
+    max_ctrl, max_model, bad_step = 0.0, 0.0, []
+    a_idle = np.asarray([ob.s.a_prev[0], ob.s.a_prev[1]])
+    for r in range(len(idx)):
+        th = (oracle.theta(seed, inst, int(idx[r]), 1, oracle.n_theta(m))[0]
+              if theta_rows is None else np.asarray(theta_rows[r], np.float64))
+        ap = np.concatenate([a_idle[None], g_ctrl[r, :T - 1]], 0)
+        st = oracle.step_at_states(m, ob, th, g_traj[r, :T], ap, np.arange(T))
+        ec = np.abs(st["a"] - g_ctrl[r]).max()
+        zn = np.empty((T, 4))
+        for h in range(T):
+            d, u = oracle.control_map(m, g_ctrl[r, h])
+            zn[h] = oracle.vehicle_step(m, g_traj[r, h], d, u)
+        em = _traj_err(g_traj[r, 1:], zn).max()
+        max_ctrl, max_model = max(max_ctrl, ec), max(max_model, em)
+        if ec > CTRL_STEP_ATOL or em > MODEL_STEP_RTOL:
+            bad_step.append((int(idx[r]), float(ec), float(em)))
+    assert not bad_step, f"per-step mismatch (sample, control err, model err): {bad_step[:10]}"
+
     # 1. conditioning
     first64 = ref["first_collision"]
     n_ill = 0
     well = np.zeros(len(idx), bool)
     for r in range(len(idx)):
         upto = (first64[r] if first64[r] >= 0 else T) + 1
-        e32 = _traj_err(r32["traj"][r, :upto], ref["traj"][r, :upto]).max()
-        c64, c32 = ref["cost"][r], r32["cost"][r]
-        if math.isinf(c64) != math.isinf(c32):
-            cbad = True
-        else:
-            cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.1 * COST_RTOL * max(c64, 1.0)
-        well[r] = e32 <= 0.1 * TRAJ_RTOL and not cbad
+        ok = True
+        for r32 in perturbed:
+            e32 = _traj_err(r32["traj"][r, :upto], ref["traj"][r, :upto]).max()
+            c64, c32 = ref["cost"][r], r32["cost"][r]
+            if math.isinf(c64) != math.isinf(c32):
+                cbad = True
+            else:
+                cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.1 * COST_RTOL * max(c64, 1.0)
+            ok = ok and e32 <= 0.1 * TRAJ_RTOL and not cbad
+        well[r] = ok
         n_ill += not well[r]
 
     # 2. trajectories and controls, 4. costs
-    bad_traj, bad_cost, face_sensitive = [], [], 0
+    bad_traj, bad_cost, face_sensitive, max_traj, max_cost = [], [], 0, 0.0, 0.0
     for r in np.flatnonzero(well):
         upto = (first64[r] if first64[r] >= 0 else T) + 1
         e = _traj_err(g_traj[r, :upto], ref["traj"][r, :upto])
+        max_traj = max(max_traj, float(e.max()))
         if e.max() > TRAJ_RTOL:
             bad_traj.append((int(idx[r]), float(e.max()), int(e.argmax())))
-            continue
-        nctl = min(upto, T)
-        ec = np.abs(g_ctrl[r, :nctl] - ref["controls"][r, :nctl]).max() if nctl else 0.0
-        if ec > CTRL_ATOL:
-            bad_traj.append((int(idx[r]), float(ec), -1))
             continue
         c64, cg = ref["cost"][r], g_cost[r]
         if math.isinf(c64) and math.isinf(cg):
@@ -125,12 +152,16 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
                 continue
             bad_cost.append((int(idx[r]), cg, c64))
             continue
-        if abs(cg - c64) > COST_RTOL * max(c64, 1.0):
+        rel = abs(cg - c64) / max(c64, 1.0)
+        max_cost = max(max_cost, rel)
+        if rel > COST_RTOL:
             bad_cost.append((int(idx[r]), cg, c64))
-    assert not bad_traj, f"trajectory/control mismatch (sample, err, step): {bad_traj[:10]}"
+    assert not bad_traj, f"trajectory mismatch (sample, err, step): {bad_traj[:10]}"
     assert not bad_cost, f"cost mismatch (sample, gpu, oracle): {bad_cost[:10]}"
     return dict(n=len(idx), ill_conditioned=n_ill, undecided=undecided,
-                face_sensitive=face_sensitive, collided=int((first64 >= 0).sum()))
+                face_sensitive=face_sensitive, collided=int((first64 >= 0).sum()),
+                max_step_ctrl_err=max_ctrl, max_step_model_err=max_model,
+                max_traj_err=max_traj, max_cost_err=max_cost)
 
 
 def _rollout_rows(m, ob, rows, fp32_state):
