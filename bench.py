@@ -91,6 +91,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of planning, run a plain device copy of this many MiB "
+                         "(reference kernel for scaling HBM counter readings)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the planner's "
@@ -103,6 +106,15 @@ def main() -> int:
     from paper_1904_06680_amd.nnplan import Planner
 
     dev = torch.device("cuda", 0)
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"copy_mib": args.copy_mib, "launches": args.steps}), flush=True)
+        return 0
     preset = scenes.C1
     pl = Planner(preset, device=0)
     scs = [scenes.scene_c1(s) for s in range(N_SCENES)]

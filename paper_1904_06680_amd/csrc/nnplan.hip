@@ -6,9 +6,10 @@
 //                          also resets the argmin key.
 //   2. rollout_kernel      every sample rolled over the horizon: Philox parameters in
 //                          registers, per step a pass over all points (eq. (2) and the nearest
-//                          distance) fed by scalar loads, features (eq. (3)), MLP (eq. (4)),
-//                          model (Sect. II-F) and the cost; a u64 (cost bits, index) atomicMin
-//                          selects the best sample, lowest index on ties.
+//                          distance) from LDS buffers filled by asynchronous copies, features
+//                          (eq. (3)), MLP (eq. (4)), model (Sect. II-F) and the cost; a u64
+//                          (cost bits, index) atomicMin selects the best sample, lowest index on
+//                          ties.
 //   3. replay_kernel       one workgroup re-simulates the winner with the same device functions
 //                          (points split over 256 lanes) and writes theta*, controls, trajectory.
 #include <hip/hip_runtime.h>
@@ -32,6 +33,8 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this (pairs per
                                 // subset then come in whole groups of eight for K <= 4)
+constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB)
+constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
 
 struct RolloutArgs {
     DevModel m;
@@ -106,22 +109,18 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
-// The obstacle pass of one lane: n consecutive point pairs p[0..n) (n a multiple of 8) against
-// one pose. p is the same for the whole wavefront, so the pairs arrive through scalar loads and
-// enter the arithmetic as scalar operands; no LDS traffic and no per-lane loads.
-typedef const __attribute__((address_space(4))) v4f const_v4f;   // read-only for the kernel
-
-__device__ __forceinline__ void point_pass(const Pose &pose, const const_v4f *p, int n, float &mm,
+// The obstacle pass of one lane: n consecutive point pairs p[0..n) in LDS (n a multiple of 8)
+// against one pose. p is the same for the whole wavefront, so every read is an LDS broadcast.
+// Two register groups of four pairs alternate: one is read while the other is tested, so the
+// LDS latency hides behind the arithmetic even at one wavefront per SIMD. The empty asm
+// statements consume a group (forcing its wait there), and the scheduling barriers keep the
+// compiler from sinking the reads next to their uses.
+__device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n, float &mm,
                                            float &md)
 {
-    // Two register groups of four pairs alternate: one is loaded while the other is tested, so
-    // the scalar loads (L2 latency on their first touch) overlap the arithmetic. Scalar loads
-    // complete out of order and can only be waited for all together, so each group is waited
-    // for (the empty asm statements that read it) before the other group's load is issued.
-    // The scheduling barriers keep the compiler from moving loads next to their uses.
     v4f a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
     for (int i = 0; i < n; i += 8) {
-        asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3));
+        asm volatile("" ::"v"(a0), "v"(a1), "v"(a2), "v"(a3));
         const v4f b0 = p[i + 4], b1 = p[i + 5], b2 = p[i + 6], b3 = p[i + 7];
         __builtin_amdgcn_sched_barrier(0);
         pose.pair(a0, mm, md);
@@ -129,7 +128,7 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const const_v4f *p,
         pose.pair(a2, mm, md);
         pose.pair(a3, mm, md);
         __builtin_amdgcn_sched_barrier(0);
-        asm volatile("" ::"s"(b0), "s"(b1), "s"(b2), "s"(b3));
+        asm volatile("" ::"v"(b0), "v"(b1), "v"(b2), "v"(b3));
         const int na = i + 8 < n ? i + 8 : i;
         a0 = p[na];
         a1 = p[na + 1];
@@ -144,26 +143,49 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const const_v4f *p,
     }
 }
 
+// Asynchronous copy of `cnt` point pairs (rounded up to whole chunks of 64) from global memory
+// into an LDS buffer: each wavefront instruction moves one chunk, lane l the pair l of it, with
+// no register staging. Completion is awaited with vmcnt before the barrier that publishes the
+// buffer.
+__device__ __forceinline__ void copy_points(const v4f *src, v4f *dst, int cnt, int wave)
+{
+    const int lane = threadIdx.x & 63;
+    for (int c = wave; c * CHUNK < cnt; c += BLOCK / 64)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(src + c * CHUNK + lane),
+            (__attribute__((address_space(3))) void *)(dst + c * CHUNK), 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_copies()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), other counters untouched
+}
+
 // ---------------------------------------------------------------------------------------------
 // 2. The rollout of every sample.
 //
 // A workgroup holds S = BLOCK / K samples. For the controller a sample occupies K adjacent lanes
 // (its weights are split over them); for the obstacle pass every lane takes one sample and one
 // K-th of the points: lane t tests sample t % S against point subset t / S, which is the same
-// for the whole wavefront. Poses go out and per-subset minima come back through LDS, two
-// workgroup barriers per step (none when K = 1, where both layouts coincide).
+// for the whole wavefront. Each step's extrapolated points stream into one of two LDS buffers
+// (at most TILE_PAIRS pairs at a time) while the previous buffer is being tested. Poses go out
+// and per-subset minima come back through LDS (none of that when K = 1, where both layouts
+// coincide).
 // ---------------------------------------------------------------------------------------------
 template <class NetT, int K, int MODE>
 __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
 {
     constexpr int S = BLOCK / K;
     static_assert(S % 64 == 0, "point subsets must be wavefront-uniform");
-    __shared__ float lds[ThetaSource::STAGE * BLOCK];   // weight staging, then pose exchange
-    float *pose_x = lds, *pose_y = lds + S, *pose_cxi = lds + 2 * S, *pose_sxi = lds + 3 * S;
-    float *pose_ceta = lds + 4 * S, *pose_seta = lds + 5 * S;
-    float *part_m = lds + 6 * S, *part_d = lds + 6 * S + BLOCK;
+    static_assert(ThetaSource::STAGE * BLOCK <= 4 * TILE_PAIRS, "weight staging fits a buffer");
+    __shared__ v4f pbuf[2][TILE_PAIRS];
+    __shared__ float xch[6 * S + 2 * BLOCK];
+    float *pose_x = xch, *pose_y = xch + S, *pose_cxi = xch + 2 * S, *pose_sxi = xch + 3 * S;
+    float *pose_ceta = xch + 4 * S, *pose_seta = xch + 5 * S;
+    float *part_m = xch + 6 * S, *part_d = xch + 6 * S + BLOCK;
 
     const int tid = threadIdx.x;
+    const int wave = tid >> 6;
     const int q = (tid & 63) % K;
     const int slot = tid / K;                                  // controller layout
     const int sample = blockIdx.x * S + slot;
@@ -173,20 +195,21 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
     const int psub = __builtin_amdgcn_readfirstlane(tid / S);
 
     SampleSim<NetT, K> sim;
-    sim.ctl.load(make_source<NetT>(a, si), q, lds, tid, BLOCK);
+    sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&pbuf[1][0]), tid, BLOCK);
     sim.init(a.z0, a.a_prev);
     __syncthreads();
 
     const int P2 = a.P2;
-    const int n_sub = P2 / K;                                  // pairs per subset, multiple of 8
+    const int ntile = (P2 + TILE_PAIRS - 1) / TILE_PAIRS;      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
     const float oxi = -a.m.oc * a.m.ihl;
+    if (ntile > 0) copy_points(ext, pbuf[0], min(P2, TILE_PAIRS), wave);
 
+    int it = 0;
     for (int h = 0; h <= a.T; ++h) {
         const Pose own = sim.begin_step(a.m);
         float mm = INFINITY, md = INFINITY;
-        if (P2 > 0) {
-            Pose pose = own;
+        if (ntile > 0) {
             if constexpr (K > 1) {
                 if (q == 0) {
                     pose_x[slot] = own.x;
@@ -196,17 +219,29 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
                     pose_ceta[slot] = own.ceta;
                     pose_seta[slot] = own.seta;
                 }
-                __syncthreads();
-                pose.x = pose_x[pslot];
-                pose.y = pose_y[pslot];
-                pose.cxi = pose_cxi[pslot];
-                pose.sxi = pose_sxi[pslot];
-                pose.oxi = oxi;
-                pose.ceta = pose_ceta[pslot];
-                pose.seta = pose_seta[pslot];
             }
-            const const_v4f *pts = (const const_v4f *)(ext + (size_t)h * P2 + (size_t)psub * n_sub);
-            point_pass(pose, pts, n_sub, mm, md);
+            Pose pose = own;
+            for (int t = 0; t < ntile; ++t, ++it) {
+                wait_copies();
+                __syncthreads();                               // buffer it & 1 (and poses) ready
+                if (t + 1 < ntile)                             // next tile of this step
+                    copy_points(ext + (size_t)h * P2 + (size_t)(t + 1) * TILE_PAIRS,
+                                pbuf[(it + 1) & 1], min(TILE_PAIRS, P2 - (t + 1) * TILE_PAIRS),
+                                wave);
+                if constexpr (K > 1) {
+                    if (t == 0) {
+                        pose.x = pose_x[pslot];
+                        pose.y = pose_y[pslot];
+                        pose.cxi = pose_cxi[pslot];
+                        pose.sxi = pose_sxi[pslot];
+                        pose.oxi = oxi;
+                        pose.ceta = pose_ceta[pslot];
+                        pose.seta = pose_seta[pslot];
+                    }
+                }
+                const int n_sub = min(TILE_PAIRS, P2 - t * TILE_PAIRS) / K;   // multiple of 8
+                point_pass(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
+            }
             if constexpr (K > 1) {
                 part_m[tid] = mm;
                 part_d[tid] = md;
@@ -219,6 +254,10 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
                     md = fminf(md, part_d[r * S + slot]);
                 }
             }
+            // The next step's first tile streams in while the controller and the model run
+            // (issued after the last LDS read of this step, so nothing here waits for it).
+            if (h < a.T)
+                copy_points(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TILE_PAIRS), wave);
         }
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
@@ -554,7 +593,7 @@ int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
     a.key.k1 = (uint32_t)(p->seed >> 32);
     a.inst = p->inst;
     a.warm_theta = p->warm_theta;
-    const size_t need = (size_t)(p->T + 1) * a.P2 * sizeof(float4);
+    const size_t need = ((size_t)(p->T + 1) * a.P2 + CHUNK) * sizeof(float4);
     if (need > h->ext_bytes) {
         if (h->d_ext) {
             e = hipStreamSynchronize(s);

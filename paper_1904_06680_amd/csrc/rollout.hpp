@@ -38,6 +38,29 @@ struct DevModel {
     float eps_xi, eps_eta, eps_phi, eps_v;
 };
 
+// tanh in binary32 for the controller's units, about 3 ulp worst case:
+//  |x| <  0.4: the odd Maclaurin series x + c3 x^3 + ... + c13 x^13, c_{2n-1} =
+//              B_{2n} 4^n (4^n - 1) / (2n)! (B: Bernoulli numbers); the first omitted term is
+//              below 4e-9 relative on this interval;
+//  |x| >= 0.4: (1 - e) / (1 + e) with e = exp(-2|x|) from the hardware base-2 exponential and
+//              reciprocal (1 ulp each); 1 - e loses at most a factor e / (1 - e) < 0.82 of the
+//              exponential's error, and large |x| gives e = 0 and exactly +-1.
+__device__ __forceinline__ float tanh_f32(float x)
+{
+    const float s = x * x;
+    float p = 3.59212803657248e-3f;                  // 21844 / 6081075
+    p = fmaf(p, s, -8.86323552990220e-3f);           // -1382 / 155925
+    p = fmaf(p, s, 2.18694885361552e-2f);            // 62 / 2835
+    p = fmaf(p, s, -5.39682539682540e-2f);           // -17 / 315
+    p = fmaf(p, s, 1.33333333333333e-1f);            // 2 / 15
+    p = fmaf(p, s, -3.33333333333333e-1f);           // -1 / 3
+    const float small = fmaf(x * s, p, x);
+    const float a = fabsf(x);
+    const float e = __builtin_amdgcn_exp2f(a * -2.88539008177793f);   // -2 / ln 2
+    const float big = (1.0f - e) * __builtin_amdgcn_rcpf(1.0f + e);
+    return a < 0.4f ? small : copysignf(big, x);
+}
+
 // MLP shape: NIN inputs, hidden widths H1 and H2 (H2 = 0: one hidden layer), 2 tanh outputs.
 // Parameters are stored layer by layer, W_l row-major [n_l][n_{l-1}] followed by b_l.
 template <int NIN_, int H1_, int H2_, int FEAT_>
@@ -148,7 +171,7 @@ struct Controller {
             float acc = b1[u];
 #pragma unroll
             for (int i = 0; i < NIN; ++i) acc = fmaf(w1[u * NIN + i], s[i], acc);
-            h1o[u] = tanhf(acc);
+            h1o[u] = tanh_f32(acc);
         }
         float h1[H1];
         gather(h1o, h1);
@@ -160,7 +183,7 @@ struct Controller {
                 float acc = b2[o];
 #pragma unroll
                 for (int i = 0; i < H1; ++i) acc = fmaf(w2[o * H1 + i], h1[i], acc);
-                h2o[o] = tanhf(acc);
+                h2o[o] = tanh_f32(acc);
             }
             gather(h2o, hl);
         } else {
@@ -173,7 +196,7 @@ struct Controller {
             float acc = bo[r];
 #pragma unroll
             for (int i = 0; i < HL; ++i) acc = fmaf(wo[r * HL + i], hl[i], acc);
-            out[r] = tanhf(acc);
+            out[r] = tanh_f32(acc);
         }
         if constexpr (K == 1) {
             a0 = out[0];

@@ -5,7 +5,7 @@ through the controller, so the comparison is made sample by sample as follows.
 
 1. Conditioning. The oracle also runs each sample twice more with float rounding injected: the
    state rounded after every step, and in addition the features and the applied controls. A
-   sample is well conditioned when both runs stay within a tenth of the tolerances below of the
+   sample is well conditioned when both runs stay within a twentieth of the tolerances below of the
    binary64 run; closed-loop trajectories and costs are compared only for well-conditioned
    samples (the excluded count is reported and bounded by the caller). Every sample, well
    conditioned or not, goes through the step-by-step check 2b and the flag check 3.
@@ -128,8 +128,8 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
             if math.isinf(c64) != math.isinf(c32):
                 cbad = True
             else:
-                cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.1 * COST_RTOL * max(c64, 1.0)
-            ok = ok and e32 <= 0.1 * TRAJ_RTOL and not cbad
+                cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.05 * COST_RTOL * max(c64, 1.0)
+            ok = ok and e32 <= 0.05 * TRAJ_RTOL and not cbad
         well[r] = ok
         n_ill += not well[r]
 
