@@ -151,7 +151,7 @@ def main() -> int:
     khash = source_hash()
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": traffic_record(khash), "kernel": "rollout_kernel<8-32-32-2, K=4>",
+            "traffic": traffic_record(khash), "kernel": "rollout_kernel<8-32-32-2, K=8>",
             "kernel_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops,
             "source_hash": khash}
     line = {

@@ -32,7 +32,7 @@ namespace {
 
 constexpr int BLOCK = 256;
 constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this (pairs per
-                                // subset then come in whole groups of eight for K <= 4)
+                                // subset then come in whole groups of four for K <= 8)
 constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB)
 constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
 
@@ -109,37 +109,45 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
-// The obstacle pass of one lane: n consecutive point pairs p[0..n) in LDS (n a multiple of 8)
+// The obstacle pass of one lane: n consecutive point pairs p[0..n) in LDS (n a multiple of 4)
 // against one pose. p is the same for the whole wavefront, so every read is an LDS broadcast.
-// Two register groups of four pairs alternate: one is read while the other is tested, so the
-// LDS latency hides behind the arithmetic even at one wavefront per SIMD. The empty asm
+// Two register groups of G pairs alternate: one is read while the other is tested, so the
+// LDS latency hides behind the arithmetic even at one wavefront per SIMD (G pairs per group:
+// four at one wavefront per SIMD, two when two wavefronts share it). The empty asm
 // statements consume a group (forcing its wait there), and the scheduling barriers keep the
 // compiler from sinking the reads next to their uses.
+template <int G>
 __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n, float &mm,
                                            float &md)
 {
-    v4f a0 = p[0], a1 = p[1], a2 = p[2], a3 = p[3];
-    for (int i = 0; i < n; i += 8) {
-        asm volatile("" ::"v"(a0), "v"(a1), "v"(a2), "v"(a3));
-        const v4f b0 = p[i + 4], b1 = p[i + 5], b2 = p[i + 6], b3 = p[i + 7];
+    static_assert(G == 2 || G == 4, "groups of two or four pairs");
+    v4f a[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) a[g] = p[g];
+    int i = 0;
+    for (; i + 2 * G <= n; i += 2 * G) {
+        if constexpr (G == 4) asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]));
+        else asm volatile("" ::"v"(a[0]), "v"(a[1]));
+        v4f b[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) b[g] = p[i + G + g];
         __builtin_amdgcn_sched_barrier(0);
-        pose.pair(a0, mm, md);
-        pose.pair(a1, mm, md);
-        pose.pair(a2, mm, md);
-        pose.pair(a3, mm, md);
+#pragma unroll
+        for (int g = 0; g < G; ++g) pose.pair(a[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
-        asm volatile("" ::"v"(b0), "v"(b1), "v"(b2), "v"(b3));
-        const int na = i + 8 < n ? i + 8 : i;
-        a0 = p[na];
-        a1 = p[na + 1];
-        a2 = p[na + 2];
-        a3 = p[na + 3];
+        if constexpr (G == 4) asm volatile("" ::"v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
+        else asm volatile("" ::"v"(b[0]), "v"(b[1]));
+        const int na = i + 2 * G < n ? i + 2 * G : i;
+#pragma unroll
+        for (int g = 0; g < G; ++g) a[g] = p[na + g];
         __builtin_amdgcn_sched_barrier(0);
-        pose.pair(b0, mm, md);
-        pose.pair(b1, mm, md);
-        pose.pair(b2, mm, md);
-        pose.pair(b3, mm, md);
+#pragma unroll
+        for (int g = 0; g < G; ++g) pose.pair(b[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (i < n) {            // a last group when n is G more than a multiple of 2G
+#pragma unroll
+        for (int g = 0; g < G; ++g) pose.pair(a[g], mm, md);
     }
 }
 
@@ -147,10 +155,11 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n
 // into an LDS buffer: each wavefront instruction moves one chunk, lane l the pair l of it, with
 // no register staging. Completion is awaited with vmcnt before the barrier that publishes the
 // buffer.
+template <int WAVES>
 __device__ __forceinline__ void copy_points(const v4f *src, v4f *dst, int cnt, int wave)
 {
     const int lane = threadIdx.x & 63;
-    for (int c = wave; c * CHUNK < cnt; c += BLOCK / 64)
+    for (int c = wave; c * CHUNK < cnt; c += WAVES)
         __builtin_amdgcn_global_load_lds(
             (const void *)(src + c * CHUNK + lane),
             (__attribute__((address_space(3))) void *)(dst + c * CHUNK), 16, 0, 0);
@@ -164,7 +173,7 @@ __device__ __forceinline__ void wait_copies()
 // ---------------------------------------------------------------------------------------------
 // 2. The rollout of every sample.
 //
-// A workgroup holds S = BLOCK / K samples. For the controller a sample occupies K adjacent lanes
+// A workgroup of RB = rollout_block(K) threads holds S = RB / K samples. For the controller a sample occupies K adjacent lanes
 // (its weights are split over them); for the obstacle pass every lane takes one sample and one
 // K-th of the points: lane t tests sample t % S against point subset t / S, which is the same
 // for the whole wavefront. Each step's extrapolated points stream into one of two LDS buffers
@@ -172,17 +181,21 @@ __device__ __forceinline__ void wait_copies()
 // and per-subset minima come back through LDS (none of that when K = 1, where both layouts
 // coincide).
 // ---------------------------------------------------------------------------------------------
+constexpr int rollout_block(int K) { return K <= 4 ? 256 : 64 * K; }
+
 template <class NetT, int K, int MODE>
-__global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
+__global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const RolloutArgs a)
 {
-    constexpr int S = BLOCK / K;
+    constexpr int RB = rollout_block(K);
+    constexpr int S = RB / K;
+    constexpr int WAVES = RB / 64;
     static_assert(S % 64 == 0, "point subsets must be wavefront-uniform");
-    static_assert(ThetaSource::STAGE * BLOCK <= 4 * TILE_PAIRS, "weight staging fits a buffer");
+    static_assert(ThetaSource::STAGE * RB <= 8 * TILE_PAIRS, "weight staging fits the buffers");
     __shared__ v4f pbuf[2][TILE_PAIRS];
-    __shared__ float xch[6 * S + 2 * BLOCK];
+    __shared__ float xch[6 * S + 2 * RB];
     float *pose_x = xch, *pose_y = xch + S, *pose_cxi = xch + 2 * S, *pose_sxi = xch + 3 * S;
     float *pose_ceta = xch + 4 * S, *pose_seta = xch + 5 * S;
-    float *part_m = xch + 6 * S, *part_d = xch + 6 * S + BLOCK;
+    float *part_m = xch + 6 * S, *part_d = xch + 6 * S + RB;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -195,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
     const int psub = __builtin_amdgcn_readfirstlane(tid / S);
 
     SampleSim<NetT, K> sim;
-    sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&pbuf[1][0]), tid, BLOCK);
+    sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&pbuf[0][0]), tid, RB);
     sim.init(a.z0, a.a_prev);
     __syncthreads();
 
@@ -203,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
     const int ntile = (P2 + TILE_PAIRS - 1) / TILE_PAIRS;      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
     const float oxi = -a.m.oc * a.m.ihl;
-    if (ntile > 0) copy_points(ext, pbuf[0], min(P2, TILE_PAIRS), wave);
+    if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TILE_PAIRS), wave);
 
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
@@ -225,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
                 wait_copies();
                 __syncthreads();                               // buffer it & 1 (and poses) ready
                 if (t + 1 < ntile)                             // next tile of this step
-                    copy_points(ext + (size_t)h * P2 + (size_t)(t + 1) * TILE_PAIRS,
+                    copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TILE_PAIRS,
                                 pbuf[(it + 1) & 1], min(TILE_PAIRS, P2 - (t + 1) * TILE_PAIRS),
                                 wave);
                 if constexpr (K > 1) {
@@ -239,8 +252,8 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
                         pose.seta = pose_seta[pslot];
                     }
                 }
-                const int n_sub = min(TILE_PAIRS, P2 - t * TILE_PAIRS) / K;   // multiple of 8
-                point_pass(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
+                const int n_sub = min(TILE_PAIRS, P2 - t * TILE_PAIRS) / K;   // multiple of 4
+                point_pass<(K >= 8 ? 2 : 4)>(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
             }
             if constexpr (K > 1) {
                 part_m[tid] = mm;
@@ -257,7 +270,8 @@ __global__ __launch_bounds__(BLOCK) void rollout_kernel(const RolloutArgs a)
             // The next step's first tile streams in while the controller and the model run
             // (issued after the last LDS read of this step, so nothing here waits for it).
             if (h < a.T)
-                copy_points(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TILE_PAIRS), wave);
+                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TILE_PAIRS),
+                                   wave);
         }
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
@@ -394,9 +408,11 @@ template <class NetT, int K>
 void launch_rollout_t(const RolloutArgs &a, int mode, dim3 grid, hipStream_t s)
 {
     if (mode == MODE_PLAN)
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN>), grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN>), grid, dim3(rollout_block(K)), 0,
+                           s, a);
     else
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT>), grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT>), grid, dim3(rollout_block(K)), 0,
+                           s, a);
 }
 
 template <class NetT, int K>
@@ -411,7 +427,8 @@ void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
      launch_replay_t<Net<NIN, H1, H2, FEAT>, K>}
 
 const Variant kVariants[] = {
-    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // 8-32-32-2, 1410 parameters
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // two wavefronts per SIMD at 8 lanes/sample)
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 1),      // 6-16-2, 146 parameters
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 2),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 4),
@@ -636,7 +653,8 @@ hipEvent_t pool_event(nnp_handle *h)
 int launch_rollout(nnp_handle *h, const RolloutArgs &a, int mode, hipStream_t s)
 {
     const long long lanes = (long long)a.N * h->var->K;
-    const dim3 grid((unsigned)((lanes + BLOCK - 1) / BLOCK));
+    const int rb = rollout_block(h->var->K);
+    const dim3 grid((unsigned)((lanes + rb - 1) / rb));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->timing) {
         e0 = pool_event(h);

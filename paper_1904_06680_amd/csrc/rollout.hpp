@@ -2,7 +2,7 @@
 // Sect. II-E (features eq. (3) -> MLP eq. (4) -> control map and kinematic model of Sect. II-F),
 // the per-point rectangle test of eq. (2) and the cost.
 //
-// Lane layout: a sample occupies K adjacent lanes of a wavefront (K in {1, 2, 4}). Each lane
+// Lane layout: a sample occupies K adjacent lanes of a wavefront (K in {1, 2, 4, 8}). Each lane
 // holds H/K rows of every hidden layer plus one row of the output layer, so a 1410-parameter
 // 8-32-32-2 network fits in registers at K = 4. The K lanes split the obstacle points of every
 // step and keep identical copies of the state; hidden activations are all-gathered with DPP lane
@@ -77,7 +77,8 @@ struct Net {
 };
 
 // ---------------------------------------------------------------------------------------------
-// Lane exchanges within a sample's K lanes (DPP quad permutations; K <= 4 stays in a quad).
+// Lane exchanges within a sample's K lanes: DPP quad permutations for K <= 4 (a quad), plus the
+// half-row mirror (lane i <-> 7 - i) and LDS-free swizzle broadcasts for K = 8.
 // ---------------------------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
@@ -90,6 +91,7 @@ __device__ __forceinline__ float group_min(float v)
 {
     if constexpr (K >= 2) v = fminf(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
     if constexpr (K >= 4) v = fminf(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (K >= 8) v = fminf(v, dpp_f<0x141>(v));  // row_half_mirror: the other quad
     return v;
 }
 
@@ -99,7 +101,9 @@ __device__ __forceinline__ float group_bcast(float v)
 {
     if constexpr (K == 1) return v;
     else if constexpr (K == 2) return dpp_f<(B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6))>(v);
-    else return dpp_f<(B * 0x55)>(v);
+    else if constexpr (K == 4) return dpp_f<(B * 0x55)>(v);
+    else   // swizzle bit mode: lane = (lane & 0b11000) | B within each 32 lanes
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (B << 5)));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -149,18 +153,29 @@ struct Controller {
         }
     }
 
-    template <int U, int W>
-    __device__ __forceinline__ static void gather(const float (&own)[U], float (&full)[W])
+    // Sub-lane B's value of a per-lane array element, as a compile-time selected broadcast.
+    template <int B>
+    __device__ __forceinline__ static float bcast(float v)
     {
+        return group_bcast<K, B>(v);
+    }
+
+    // acc[o] += sum_j W[o][j] x[j] over the full input vector x of width U * K, whose element
+    // j = b * U + u lives in sub-lane b as own[u]. Elements are broadcast one at a time and
+    // consumed in index order (so no gathered copy of x is kept and the summation order is
+    // the same for every K).
+    template <int NOUT, int U, int B = 0>
+    __device__ __forceinline__ static void accumulate(const float *W, const float (&own)[U],
+                                                      float (&acc)[NOUT])
+    {
+        constexpr int NINP = U * K;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            full[0 * U + u] = group_bcast<K, 0>(own[u]);
-            if constexpr (K >= 2) full[1 * U + u] = group_bcast<K, 1>(own[u]);
-            if constexpr (K >= 4) {
-                full[2 * U + u] = group_bcast<K, 2>(own[u]);
-                full[3 * U + u] = group_bcast<K, 3>(own[u]);
-            }
+            const float x = bcast<B>(own[u]);
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) acc[o] = fmaf(W[o * NINP + B * U + u], x, acc[o]);
         }
+        if constexpr (B + 1 < K) accumulate<NOUT, U, B + 1>(W, own, acc);
     }
 
     __device__ __forceinline__ void forward(const float (&s)[NIN], float &a0, float &a1) const
@@ -173,31 +188,22 @@ struct Controller {
             for (int i = 0; i < NIN; ++i) acc = fmaf(w1[u * NIN + i], s[i], acc);
             h1o[u] = tanh_f32(acc);
         }
-        float h1[H1];
-        gather(h1o, h1);
-        float hl[HL];
+        float out[NO];
+#pragma unroll
+        for (int r = 0; r < NO; ++r) out[r] = bo[r];
         if constexpr (H2) {
             float h2o[U2];
 #pragma unroll
-            for (int o = 0; o < U2; ++o) {
-                float acc = b2[o];
+            for (int o = 0; o < U2; ++o) h2o[o] = b2[o];
+            accumulate<U2, U1>(w2, h1o, h2o);
 #pragma unroll
-                for (int i = 0; i < H1; ++i) acc = fmaf(w2[o * H1 + i], h1[i], acc);
-                h2o[o] = tanh_f32(acc);
-            }
-            gather(h2o, hl);
+            for (int o = 0; o < U2; ++o) h2o[o] = tanh_f32(h2o[o]);
+            accumulate<NO, U2>(wo, h2o, out);
         } else {
-#pragma unroll
-            for (int i = 0; i < HL; ++i) hl[i] = h1[i];
+            accumulate<NO, U1>(wo, h1o, out);
         }
-        float out[NO];
 #pragma unroll
-        for (int r = 0; r < NO; ++r) {
-            float acc = bo[r];
-#pragma unroll
-            for (int i = 0; i < HL; ++i) acc = fmaf(wo[r * HL + i], hl[i], acc);
-            out[r] = tanh_f32(acc);
-        }
+        for (int r = 0; r < NO; ++r) out[r] = tanh_f32(out[r]);
         if constexpr (K == 1) {
             a0 = out[0];
             a1 = out[1];
@@ -208,8 +214,6 @@ struct Controller {
     }
 };
 
-// ---------------------------------------------------------------------------------------------
-// One sample's closed-loop state.
 // ---------------------------------------------------------------------------------------------
 // The vehicle pose at one step in the form the obstacle pass consumes.
 // ---------------------------------------------------------------------------------------------
@@ -236,8 +240,8 @@ struct Pose {
         float m0, d0, m1, d1;
         point(p.x, p.y, m0, d0);
         point(p.z, p.w, m1, d1);
-        mm = fminf(mm, fminf(m0, m1));
-        md = fminf(md, fminf(d0, d1));
+        mm = fminf(fminf(mm, m0), m1);   // one v_min3 per pair
+        md = fminf(fminf(md, d0), d1);
     }
 };
 
