@@ -70,7 +70,7 @@ typedef struct nnp_model {
     float d_cap;                     /* cap of the nearest-obstacle distance feature [m]        */
     float effort_weight;             /* cost = |p_T - g_xy| + effort_weight*T_s*sum|a_h|^2     */
     float eps_xi, eps_eta, eps_phi, eps_v; /* goal tolerances for the goal_reached flag          */
-    int32_t lanes_per_sample;        /* 0 = library default for the network; else 1, 2, 4, 8    */
+    int32_t lanes_per_sample;        /* 0 = library default for the network; 1, 2, 4, 8, 16    */
 } nnp_model;
 
 /* One planning problem at sampling time t (Sect. II-E, fourth comment: what is passed to the GPU
@@ -134,6 +134,23 @@ int nnp_n_theta(const nnp_handle *h);
  * the lowest-cost one (lowest index on ties) with its controls and trajectory. Every sample is
  * simulated over the whole horizon. */
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
+
+/* Many independent problems in one call: the same plan as nnp_plan for every probs[i] (each with
+ * its own N, T, P, obstacles, seed and warm start), written to results[i]. All problems are
+ * rolled out by one persistent launch that drains a work queue of (problem, block of samples)
+ * items, longest problems first, so uneven sizes share the GPU without a launch per problem.
+ * The call copies `count` problem descriptors to the device through a pinned staging buffer
+ * owned by the handle (it waits for the previous batch's copy before reusing it) and enqueues
+ * three kernels. Results are bit-identical to nnp_plan on each problem and to every lane layout.
+ * Returns NNP_EINVAL if count < 1 or any problem is invalid (nnp_last_error names it).
+ * HIP graph capture: the call records one host-to-device copy from the staging buffer and three
+ * kernels (no memsets, no host synchronisation). The handle's batch workspace must already be
+ * large enough, i.e. an uncaptured call with at least as many problems, samples-times-points and
+ * table entries must come first, else NNP_EINVAL. Replays re-read the staging buffer, so between
+ * the capture and the graph's last replay no other nnp_plan_batch call may be made on the same
+ * handle (use a second handle for other batches); nnp_plan and nnp_rollout do not touch it. */
+int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_result *results,
+                   void *hip_stream);
 
 /* Same rollout kernel as nnp_plan, with per-sample outputs instead of the argmin. theta, if not
  * NULL, is a device [N][n_theta] array of parameters used instead of the Philox draws (explicit-

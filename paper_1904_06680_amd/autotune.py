@@ -1,0 +1,72 @@
+"""Autotuner for the lane layout (samples per workgroup tile) of batched planning.
+
+The rollout kernel comes in several layouts for one network: K lanes per sample (4, 8 or 16 for
+the 8-32-32-2 controller), which fixes the workgroup size, the samples per work item and the
+wavefronts per SIMD. All layouts give bit-identical results, so the choice is purely a matter of
+speed on the given batch shape; this module times each candidate on the caller's batch and
+returns the fastest, optionally caching the answer per device and batch signature.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from .nnplan import NnpError, Planner
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "nnplan", "autotune.json")
+
+
+def signature(preset: dict, scenes_, Ns) -> str:
+    """Coarse key of a batch shape: network, count, and size buckets of N, P and T."""
+    b = lambda v: int(round(v)).bit_length()  # noqa: E731
+    tot = sum(N * (sc.T + 1) * max(sc.P, 1) for sc, N in zip(scenes_, Ns))
+    return "w{}-c{}-w{}".format("x".join(map(str, preset["widths"])), len(Ns), b(tot))
+
+
+def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: int = 3,
+               device: int = 0, cache: str | None = None) -> dict:
+    import torch
+    dev = torch.device("cuda", device)
+    key = f"{torch.cuda.get_device_name(dev)}|{signature(preset, scenes_, Ns)}"
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as fh:
+                known = json.load(fh)
+            if key in known:
+                return dict(known[key], cached=True)
+        except (OSError, ValueError):
+            pass
+    timings = {}
+    for K in candidates:
+        try:
+            pl = Planner(preset, device=device, lanes_per_sample=K)
+        except NnpError:
+            continue
+        probs, keep = pl.batch_problems(scenes_, Ns, seeds)
+        outs = [pl.alloc_result(sc.T) for sc in scenes_]
+        pl.plan_batch_async(probs, outs)          # warm-up (sizes the workspace)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pl.plan_batch_async(probs, outs)
+        torch.cuda.synchronize(dev)
+        timings[K] = (time.perf_counter() - t0) / reps * 1e3
+        del keep
+        pl.close()
+    best = min(timings, key=timings.get)
+    res = {"lanes_per_sample": best, "ms": timings[best],
+           "timings_ms": {str(k): v for k, v in timings.items()}, "key": key}
+    if cache:
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            known = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    known = json.load(fh)
+            known[key] = res
+            with open(cache, "w") as fh:
+                json.dump(known, fh, indent=1)
+        except (OSError, ValueError):
+            pass
+    return dict(res, cached=False)

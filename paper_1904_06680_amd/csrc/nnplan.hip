@@ -18,6 +18,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -33,7 +34,8 @@ namespace {
 constexpr int BLOCK = 256;
 constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this (pairs per
                                 // subset then come in whole groups of four for K <= 8)
-constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB)
+constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB); 1536 for
+                                  // K = 16, so that three workgroups share a CU
 constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
 
 struct RolloutArgs {
@@ -49,6 +51,8 @@ struct RolloutArgs {
     float *cost;                     // rollout mode outputs (each may be null)
     int32_t *collided, *first;
     float *min_margin, *traj, *controls;
+    const float4 *obst;              // raw points [P][4] (batched extrapolation)
+    int P;
 };
 
 struct ReplayOut {
@@ -77,6 +81,31 @@ __global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__rest
     const float4 b = pts[min(2 * j + 1, P - 1)];
     ext[gid] = make_float4(fmaf(t, a.z, a.x), fmaf(t, a.w, a.y), fmaf(t, b.z, b.x),
                            fmaf(t, b.w, b.y));
+}
+
+// The same table for every problem of a batch: blockIdx.y is the problem, the x blocks stride
+// over its entries. Also resets the problems' argmin keys and the work-queue counter.
+__global__ __launch_bounds__(BLOCK) void extrapolate_batch_kernel(const RolloutArgs *probs,
+                                                                  unsigned *counter)
+{
+    const RolloutArgs &a = probs[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *a.best_key = ~0ull;
+        if (blockIdx.y == 0) *counter = 0u;
+    }
+    if (a.P == 0) return;
+    const long long n = (long long)(a.T + 1) * a.P2;
+    float4 *ext = const_cast<float4 *>(a.ext);
+    for (long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x; gid < n;
+         gid += (long long)gridDim.x * BLOCK) {
+        const int h = (int)(gid / a.P2);
+        const int j = (int)(gid % a.P2);
+        const float t = (float)h * a.m.dt;
+        const float4 p = a.obst[min(2 * j, a.P - 1)];
+        const float4 q = a.obst[min(2 * j + 1, a.P - 1)];
+        ext[gid] = make_float4(fmaf(t, p.z, p.x), fmaf(t, p.w, p.y), fmaf(t, q.z, q.x),
+                               fmaf(t, q.w, q.y));
+    }
 }
 
 template <class NetT>
@@ -181,31 +210,41 @@ __device__ __forceinline__ void wait_copies()
 // and per-subset minima come back through LDS (none of that when K = 1, where both layouts
 // coincide).
 // ---------------------------------------------------------------------------------------------
-constexpr int rollout_block(int K) { return K <= 4 ? 256 : 64 * K; }
+constexpr int rollout_block(int K) { return K == 8 ? 512 : 256; }
+constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
 
+constexpr int rollout_waves_per_eu(int K) { return K >= 16 ? 3 : 1; }
+
+// LDS of one rollout workgroup.
+template <int K>
+struct RolloutShared {
+    static constexpr int RB = rollout_block(K), S = RB / K, TP = tile_pairs(K);
+    v4f pbuf[2][TP];                 // point pairs of the current / next tile
+    v4f pose[2 * S];                 // poses out (two float4 per sample)
+    float part[2 * RB];              // per-subset minima back
+};
+
+// The rollout of samples [tile * S, tile * S + S) of one problem by one workgroup.
 template <class NetT, int K, int MODE>
-__global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const RolloutArgs a)
+__device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, RolloutShared<K> &sh)
 {
     constexpr int RB = rollout_block(K);
     constexpr int S = RB / K;
     constexpr int WAVES = RB / 64;
-    static_assert(S % 64 == 0, "point subsets must be wavefront-uniform");
-    static_assert(ThetaSource::STAGE * RB <= 8 * TILE_PAIRS, "weight staging fits the buffers");
-    __shared__ v4f pbuf[2][TILE_PAIRS];
-    __shared__ float xch[6 * S + 2 * RB];
-    float *pose_x = xch, *pose_y = xch + S, *pose_cxi = xch + 2 * S, *pose_sxi = xch + 3 * S;
-    float *pose_ceta = xch + 4 * S, *pose_seta = xch + 5 * S;
-    float *part_m = xch + 6 * S, *part_d = xch + 6 * S + RB;
+    constexpr int TP = tile_pairs(K);
+    static_assert(S % 16 == 0, "point subsets must be whole DPP rows");
+    static_assert(ThetaSource::STAGE * RB <= 8 * TP, "weight staging fits the buffers");
+    auto &pbuf = sh.pbuf;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int q = (tid & 63) % K;
     const int slot = tid / K;                                  // controller layout
-    const int sample = blockIdx.x * S + slot;
+    const int sample = tile * S + slot;
     const bool active = sample < a.N;
     const int si = active ? sample : a.N - 1;
     const int pslot = tid % S;                                 // obstacle-pass layout
-    const int psub = __builtin_amdgcn_readfirstlane(tid / S);
+    const int psub = tid / S;
 
     SampleSim<NetT, K> sim;
     sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&pbuf[0][0]), tid, RB);
@@ -213,10 +252,10 @@ __global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const Rollout
     __syncthreads();
 
     const int P2 = a.P2;
-    const int ntile = (P2 + TILE_PAIRS - 1) / TILE_PAIRS;      // 0 when there are no points
+    const int ntile = (P2 + TP - 1) / TP;                      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
     const float oxi = -a.m.oc * a.m.ihl;
-    if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TILE_PAIRS), wave);
+    if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TP), wave);
 
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
@@ -225,12 +264,8 @@ __global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const Rollout
         if (ntile > 0) {
             if constexpr (K > 1) {
                 if (q == 0) {
-                    pose_x[slot] = own.x;
-                    pose_y[slot] = own.y;
-                    pose_cxi[slot] = own.cxi;
-                    pose_sxi[slot] = own.sxi;
-                    pose_ceta[slot] = own.ceta;
-                    pose_seta[slot] = own.seta;
+                    sh.pose[2 * slot] = v4f{own.x, own.y, own.cxi, own.sxi};
+                    sh.pose[2 * slot + 1] = v4f{own.ceta, own.seta, 0.0f, 0.0f};
                 }
             }
             Pose pose = own;
@@ -238,40 +273,42 @@ __global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const Rollout
                 wait_copies();
                 __syncthreads();                               // buffer it & 1 (and poses) ready
                 if (t + 1 < ntile)                             // next tile of this step
-                    copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TILE_PAIRS,
-                                pbuf[(it + 1) & 1], min(TILE_PAIRS, P2 - (t + 1) * TILE_PAIRS),
-                                wave);
+                    copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TP,
+                                       pbuf[(it + 1) & 1], min(TP, P2 - (t + 1) * TP), wave);
                 if constexpr (K > 1) {
                     if (t == 0) {
-                        pose.x = pose_x[pslot];
-                        pose.y = pose_y[pslot];
-                        pose.cxi = pose_cxi[pslot];
-                        pose.sxi = pose_sxi[pslot];
+                        const v4f p0 = sh.pose[2 * pslot], p1 = sh.pose[2 * pslot + 1];
+                        pose.x = p0.x;
+                        pose.y = p0.y;
+                        pose.cxi = p0.z;
+                        pose.sxi = p0.w;
                         pose.oxi = oxi;
-                        pose.ceta = pose_ceta[pslot];
-                        pose.seta = pose_seta[pslot];
+                        pose.ceta = p1.x;
+                        pose.seta = p1.y;
                     }
                 }
-                const int n_sub = min(TILE_PAIRS, P2 - t * TILE_PAIRS) / K;   // multiple of 4
+                const int n_sub = min(TP, P2 - t * TP) / K;   // multiple of 2 (of 4 for K <= 8)
                 point_pass<(K >= 8 ? 2 : 4)>(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
             }
             if constexpr (K > 1) {
-                part_m[tid] = mm;
-                part_d[tid] = md;
+                sh.part[2 * tid] = mm;                     // interleaved (margin, distance)
+                sh.part[2 * tid + 1] = md;
                 __syncthreads();
-                mm = part_m[slot];
-                md = part_d[slot];
+                const float2 *pp = reinterpret_cast<const float2 *>(sh.part) + slot;
+                float2 v = pp[0];
+                mm = v.x;
+                md = v.y;
 #pragma unroll
                 for (int r = 1; r < K; ++r) {
-                    mm = fminf(mm, part_m[r * S + slot]);
-                    md = fminf(md, part_d[r * S + slot]);
+                    v = pp[r * S];                         // one base register, immediate offsets
+                    mm = fminf(mm, v.x);
+                    md = fminf(md, v.y);
                 }
             }
             // The next step's first tile streams in while the controller and the model run
             // (issued after the last LDS read of this step, so nothing here waits for it).
             if (h < a.T)
-                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TILE_PAIRS),
-                                   wave);
+                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TP), wave);
         }
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
@@ -309,15 +346,45 @@ __global__ __launch_bounds__(rollout_block(K)) void rollout_kernel(const Rollout
     }
 }
 
+
+template <class NetT, int K, int MODE>
+__global__ __launch_bounds__(rollout_block(K))
+__attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_kernel(const RolloutArgs a)
+{
+    __shared__ RolloutShared<K> sh;
+    rollout_tile<NetT, K, MODE>(a, blockIdx.x, sh);
+}
+
+// NEXT: many problems of uneven size in one persistent launch. Work items (problem, tile) are
+// taken from a global counter in the order the host wrote them (longest first); every
+// workgroup loops until the list is exhausted, so every wave reaches the exit.
+template <class NetT, int K>
+__global__ __launch_bounds__(rollout_block(K))
+__attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_batch_kernel(
+    const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items, int n_items,
+    unsigned *counter)
+{
+    __shared__ RolloutShared<K> sh;
+    __shared__ int cur;
+    for (;;) {
+        __syncthreads();                       // the previous item is done with the LDS
+        if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int w = cur;
+        if (w >= n_items) break;
+        const int2 item = items[w];
+        rollout_tile<NetT, K, MODE_PLAN>(probs[item.x], item.y, sh);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // 3. Winner replay: every lane simulates the best sample; points are split over the workgroup
 //    and reduced exactly (min), so the replay reproduces the rollout bit for bit.
 // ---------------------------------------------------------------------------------------------
 template <class NetT, int K>
-__global__ __launch_bounds__(BLOCK) void replay_kernel(const RolloutArgs a, const ReplayOut o)
+__device__ __forceinline__ void replay_body(const RolloutArgs &a, const ReplayOut &o,
+                                            float (&red)[2][BLOCK / 64], float *stage)
 {
-    __shared__ float red[2][BLOCK / 64];
-    __shared__ float stage[ThetaSource::STAGE * BLOCK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane % K;
     const unsigned long long key = *a.best_key;
@@ -379,6 +446,23 @@ __global__ __launch_bounds__(BLOCK) void replay_kernel(const RolloutArgs a, cons
         for (int k = tid; k < NetT::NTHETA; k += BLOCK) o.theta[k] = src.one(k);
 }
 
+template <class NetT, int K>
+__global__ __launch_bounds__(BLOCK) void replay_kernel(const RolloutArgs a, const ReplayOut o)
+{
+    __shared__ float red[2][BLOCK / 64];
+    __shared__ float stage[ThetaSource::STAGE * BLOCK];
+    replay_body<NetT, K>(a, o, red, stage);
+}
+
+template <class NetT, int K>
+__global__ __launch_bounds__(BLOCK) void replay_batch_kernel(const RolloutArgs *probs,
+                                                             const ReplayOut *outs)
+{
+    __shared__ float red[2][BLOCK / 64];
+    __shared__ float stage[ThetaSource::STAGE * BLOCK];
+    replay_body<NetT, K>(probs[blockIdx.x], outs[blockIdx.x], red, stage);
+}
+
 __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,
                                                       uint32_t N, uint32_t nt,
                                                       float *__restrict__ out)
@@ -402,6 +486,10 @@ struct Variant {
     int n_layers, feature_set, K, ntheta;
     void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
+    void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int, unsigned *, int grid,
+                                 hipStream_t);
+    void (*launch_replay_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
+    int (*batch_blocks_per_cu)();
 };
 
 template <class NetT, int K>
@@ -421,14 +509,44 @@ void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
     hipLaunchKernelGGL((replay_kernel<NetT, K>), dim3(1), dim3(BLOCK), 0, s, a, o);
 }
 
+template <class NetT, int K>
+void launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items,
+                            unsigned *counter, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((rollout_batch_kernel<NetT, K>), dim3(grid), dim3(rollout_block(K)), 0, s,
+                       probs, items, n_items, counter);
+}
+
+template <class NetT, int K>
+void launch_replay_batch_t(const RolloutArgs *probs, const ReplayOut *outs, int count,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((replay_batch_kernel<NetT, K>), dim3(count), dim3(BLOCK), 0, s, probs,
+                       outs);
+}
+
+template <class NetT, int K>
+int batch_blocks_per_cu_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rollout_batch_kernel<NetT, K>,
+                                                     rollout_block(K), 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
 #define NNP_VARIANT(NIN, H1, H2, FEAT, K)                                                         \
     {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, K,                              \
      Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, K>,                  \
-     launch_replay_t<Net<NIN, H1, H2, FEAT>, K>}
+     launch_replay_t<Net<NIN, H1, H2, FEAT>, K>,                                                   \
+     launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                            \
+     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                             \
+     batch_blocks_per_cu_t<Net<NIN, H1, H2, FEAT>, K>}
 
 const Variant kVariants[] = {
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // two wavefronts per SIMD at 8 lanes/sample)
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 16),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 1),      // 6-16-2, 146 parameters
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 2),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 4),
@@ -463,6 +581,12 @@ struct nnp_handle {
     unsigned long long *d_key = nullptr;
     float4 *d_ext = nullptr;
     size_t ext_bytes = 0;
+    // batched planning: tables, keys, work-queue counter, descriptors (device and pinned host)
+    void *d_bext = nullptr, *d_bkeys = nullptr, *d_bmeta = nullptr, *h_bmeta = nullptr;
+    size_t bext_bytes = 0, bkeys_bytes = 0, bmeta_bytes = 0, hmeta_bytes = 0;
+    unsigned *d_counter = nullptr;
+    hipEvent_t meta_copied = nullptr;
+    int num_cus = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -518,8 +642,8 @@ int check_model(const nnp_model *m, std::string &why)
         return NNP_EINVAL;
     }
     const int K = m->lanes_per_sample;
-    if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8) {
-        why = "lanes_per_sample must be 0, 1, 2, 4 or 8";
+    if (K != 0 && K != 1 && K != 2 && K != 4 && K != 8 && K != 16) {
+        why = "lanes_per_sample must be 0, 1, 2, 4, 8 or 16";
         return NNP_EINVAL;
     }
     if (!find_variant(m, K)) {
@@ -581,13 +705,11 @@ int check_problem(nnp_handle *h, const nnp_problem *p)
     return NNP_OK;
 }
 
-// Build the launch arguments and the extrapolation table for one problem.
-int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
+// Launch arguments of one problem (validated), without its extrapolation table.
+int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
 {
     int rc = check_problem(h, p);
     if (rc) return rc;
-    hipError_t e = hipSetDevice(h->device);
-    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
     memset(&a, 0, sizeof a);
     a.m = h->dm;
     for (int i = 0; i < 4; ++i) {
@@ -610,22 +732,43 @@ int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
     a.key.k1 = (uint32_t)(p->seed >> 32);
     a.inst = p->inst;
     a.warm_theta = p->warm_theta;
-    const size_t need = ((size_t)(p->T + 1) * a.P2 + CHUNK) * sizeof(float4);
-    if (need > h->ext_bytes) {
-        if (h->d_ext) {
-            e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-            hipFree(h->d_ext);
-            h->d_ext = nullptr;
-            h->ext_bytes = 0;
-        }
-        e = hipMalloc(&h->d_ext, need);
-        if (e != hipSuccess) {
-            h->d_ext = nullptr;
-            return fail(h, NNP_ENOMEM, "hipMalloc of the extrapolation table failed");
-        }
-        h->ext_bytes = need;
+    a.obst = reinterpret_cast<const float4 *>(p->obst);
+    a.P = p->P;
+    return NNP_OK;
+}
+
+// Extrapolation-table entries of one problem, with the slack the LDS copies may read past it.
+size_t table_entries(const RolloutArgs &a) { return (size_t)(a.T + 1) * a.P2 + CHUNK; }
+
+// Grow a device buffer (contents are not kept). Synchronises the stream before freeing.
+int grow(nnp_handle *h, void **buf, size_t *cap, size_t need, hipStream_t s, const char *what)
+{
+    if (need <= *cap) return NNP_OK;
+    if (*buf) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+        hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
     }
+    if (hipMalloc(buf, need) != hipSuccess) {
+        *buf = nullptr;
+        return fail(h, NNP_ENOMEM, std::string("hipMalloc failed: ") + what);
+    }
+    *cap = need;
+    return NNP_OK;
+}
+
+// Build the launch arguments and the extrapolation table for one problem.
+int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
+{
+    int rc = fill_args(h, p, a);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    rc = grow(h, reinterpret_cast<void **>(&h->d_ext), &h->ext_bytes,
+              table_entries(a) * sizeof(float4), s, "extrapolation table");
+    if (rc) return rc;
     a.ext = h->d_ext;
     a.best_key = h->d_key;
     const long long n = (long long)(p->T + 1) * a.P2;
@@ -718,6 +861,12 @@ void nnp_destroy(nnp_handle *h)
     for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
     if (h->d_ext) hipFree(h->d_ext);
     if (h->d_key) hipFree(h->d_key);
+    if (h->d_bext) hipFree(h->d_bext);
+    if (h->d_bkeys) hipFree(h->d_bkeys);
+    if (h->d_bmeta) hipFree(h->d_bmeta);
+    if (h->d_counter) hipFree(h->d_counter);
+    if (h->h_bmeta) hipHostFree(h->h_bmeta);
+    if (h->meta_copied) hipEventDestroy(h->meta_copied);
     delete h;
 }
 
@@ -738,6 +887,114 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
     h->var->launch_replay(a, o, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "replay_kernel launch");
+    h->err.clear();
+    return NNP_OK;
+}
+
+int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_result *results,
+                   void *hip_stream)
+{
+    if (!h) return NNP_EINVAL;
+    if (!probs || !results || count < 1) return fail(h, NNP_EINVAL, "empty batch");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+    std::vector<RolloutArgs> args((size_t)count);
+    size_t entries = 0;
+    for (int i = 0; i < count; ++i) {
+        int rc = fill_args(h, &probs[i], args[i]);
+        if (rc) return fail(h, rc, "problem " + std::to_string(i) + ": " + h->err);
+        entries += table_entries(args[i]);
+    }
+    const int K = h->var->K;
+    const int S = rollout_block(K) / K;
+    // Work items, longest problems first: (problem, tile of S samples).
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    auto work = [&](int i) { return (double)(args[i].T + 1) * (args[i].P2 + 64); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+    std::vector<int2> items;
+    for (int i : order)
+        for (int t = 0; t * S < args[i].N; ++t) items.push_back(make_int2(i, t));
+    const int n_items = (int)items.size();
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    const size_t meta = (size_t)count * (sizeof(RolloutArgs) + sizeof(ReplayOut)) +
+                        (size_t)n_items * sizeof(int2);
+    if (capturing && (entries * sizeof(float4) > h->bext_bytes || (size_t)count * 8 >
+                      h->bkeys_bytes || meta > h->bmeta_bytes || meta > h->hmeta_bytes ||
+                      !h->d_counter || !h->meta_copied || !h->num_cus))
+        return fail(h, NNP_EINVAL, "the batch workspace must be sized by an uncaptured call "
+                                   "with at least this batch before capture");
+    // Device workspace.
+    int rc = grow(h, &h->d_bext, &h->bext_bytes, entries * sizeof(float4), s, "batch tables");
+    if (!rc) rc = grow(h, &h->d_bkeys, &h->bkeys_bytes, (size_t)count * 8, s, "batch keys");
+    if (!rc) rc = grow(h, &h->d_bmeta, &h->bmeta_bytes, meta, s, "batch descriptors");
+    if (rc) return rc;
+    if (!h->d_counter && hipMalloc(&h->d_counter, sizeof(unsigned)) != hipSuccess)
+        return fail(h, NNP_ENOMEM, "hipMalloc of the work counter failed");
+    if (!h->meta_copied && hipEventCreateWithFlags(&h->meta_copied, hipEventDisableTiming) !=
+                               hipSuccess)
+        return fail(h, NNP_EDEVICE, "hipEventCreate failed");
+    // The pinned staging buffer is reused: wait until the previous batch's copy has read it
+    // (under stream capture nothing runs yet, and the caller orders its replays).
+    if (!capturing) {
+        e = hipEventSynchronize(h->meta_copied);
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
+    }
+    if (meta > h->hmeta_bytes) {
+        if (h->h_bmeta) hipHostFree(h->h_bmeta);
+        h->h_bmeta = nullptr;
+        h->hmeta_bytes = 0;
+        if (hipHostMalloc(&h->h_bmeta, meta, hipHostMallocDefault) != hipSuccess)
+            return fail(h, NNP_ENOMEM, "hipHostMalloc of the batch staging buffer failed");
+        h->hmeta_bytes = meta;
+    }
+    char *dmeta = static_cast<char *>(h->d_bmeta);
+    RolloutArgs *d_args = reinterpret_cast<RolloutArgs *>(dmeta);
+    ReplayOut *d_outs = reinterpret_cast<ReplayOut *>(dmeta + (size_t)count * sizeof(RolloutArgs));
+    int2 *d_items = reinterpret_cast<int2 *>(dmeta + (size_t)count *
+                                                         (sizeof(RolloutArgs) + sizeof(ReplayOut)));
+    char *hmeta = static_cast<char *>(h->h_bmeta);
+    RolloutArgs *h_args = reinterpret_cast<RolloutArgs *>(hmeta);
+    ReplayOut *h_outs = reinterpret_cast<ReplayOut *>(hmeta + (size_t)count * sizeof(RolloutArgs));
+    int2 *h_items = reinterpret_cast<int2 *>(hmeta + (size_t)count *
+                                                         (sizeof(RolloutArgs) + sizeof(ReplayOut)));
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        args[i].ext = static_cast<float4 *>(h->d_bext) + off;
+        off += table_entries(args[i]);
+        args[i].best_key = static_cast<unsigned long long *>(h->d_bkeys) + i;
+        h_args[i] = args[i];
+        const nnp_result &r = results[i];
+        h_outs[i] = ReplayOut{r.theta, r.controls, r.controls_phys, r.traj, r.cost, r.best_index,
+                              r.status, r.goal_reached};
+    }
+    memcpy(h_items, items.data(), items.size() * sizeof(int2));
+    e = hipMemcpyAsync(dmeta, hmeta, meta, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync of the batch descriptors");
+    if (!capturing) {
+        e = hipEventRecord(h->meta_copied, s);
+        if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
+    }
+    hipLaunchKernelGGL(extrapolate_batch_kernel, dim3(64, count), dim3(BLOCK), 0, s, d_args,
+                       h->d_counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "extrapolate_batch_kernel launch");
+    if (!h->num_cus) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) return fail(h, NNP_EDEVICE, "props");
+        h->num_cus = prop.multiProcessorCount;
+    }
+    const int grid = std::min(n_items, h->num_cus * h->var->batch_blocks_per_cu());
+    h->var->launch_rollout_batch(d_args, d_items, n_items, h->d_counter, grid, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "rollout_batch_kernel launch");
+    h->var->launch_replay_batch(d_args, d_outs, count, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "replay_batch_kernel launch");
     h->err.clear();
     return NNP_OK;
 }

@@ -107,6 +107,27 @@ struct ThetaSource {
         }
     }
 
+    // dst[e] = theta[base + e] for a short slice (COUNT even) whose base is even: its pairs never
+    // straddle a Philox block.
+    template <int COUNT>
+    __device__ __forceinline__ void fill_even(float (&dst)[COUNT], int base) const
+    {
+        static_assert(COUNT % 2 == 0, "pairs of parameters");
+        if (explicit_theta) {
+#pragma unroll
+            for (int e = 0; e < COUNT; ++e) dst[e] = explicit_theta[base + e];
+            return;
+        }
+#pragma unroll
+        for (int e = 0; e < COUNT; e += 2) {
+            const int k = base + e;
+            const uint4 w = block4(k >> 2);
+            const bool hi = (k & 2) != 0;
+            dst[e] = theta_from_word(hi ? w.z : w.x);
+            dst[e + 1] = theta_from_word(hi ? w.w : w.y);
+        }
+    }
+
     // dst[e] = theta[BASE + e] for a compile-time base of any alignment.
     template <int BASE, int COUNT>
     __device__ __forceinline__ void fill_const(float (&dst)[COUNT]) const

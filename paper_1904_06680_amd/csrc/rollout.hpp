@@ -78,7 +78,8 @@ struct Net {
 
 // ---------------------------------------------------------------------------------------------
 // Lane exchanges within a sample's K lanes: DPP quad permutations for K <= 4 (a quad), plus the
-// half-row mirror (lane i <-> 7 - i) and LDS-free swizzle broadcasts for K = 8.
+// half-row mirror (lane i <-> 7 - i) and swizzle broadcasts for K = 8, row mirror and row
+// broadcasts for K = 16 (one DPP row per sample).
 // ---------------------------------------------------------------------------------------------
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
@@ -92,6 +93,7 @@ __device__ __forceinline__ float group_min(float v)
     if constexpr (K >= 2) v = fminf(v, dpp_f<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
     if constexpr (K >= 4) v = fminf(v, dpp_f<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
     if constexpr (K >= 8) v = fminf(v, dpp_f<0x141>(v));  // row_half_mirror: the other quad
+    if constexpr (K >= 16) v = fminf(v, dpp_f<0x140>(v)); // row_mirror: the other half-row
     return v;
 }
 
@@ -102,8 +104,10 @@ __device__ __forceinline__ float group_bcast(float v)
     if constexpr (K == 1) return v;
     else if constexpr (K == 2) return dpp_f<(B | (B << 2) | ((2 + B) << 4) | ((2 + B) << 6))>(v);
     else if constexpr (K == 4) return dpp_f<(B * 0x55)>(v);
-    else   // swizzle bit mode: lane = (lane & 0b11000) | B within each 32 lanes
+    else if constexpr (K == 8)   // swizzle bit mode: lane = (lane & 0b11000) | B within 32 lanes
         return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x18 | (B << 5)));
+    else                         // K = 16, one DPP row: row_newbcast of lane B
+        return dpp_f<0x150 + B>(v);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -116,11 +120,11 @@ struct Controller {
     static constexpr int U2 = H2 ? H2 / K : 1;
     static constexpr int NO = K == 1 ? 2 : 1;       // output rows held by this lane
     static_assert(H1 % K == 0 && (H2 == 0 || H2 % K == 0), "hidden widths must split over K");
-    static_assert(K == 1 || ((U1 * NIN) % 4 == 0 && NetT::OFF_B1 % 4 == 0 && U1 % 4 == 0 &&
+    static_assert(K == 1 || ((U1 * NIN) % 4 == 0 && NetT::OFF_B1 % 4 == 0 && U1 % 2 == 0 &&
                              NetT::OFF_WO % 4 == 0 && HL % 4 == 0 &&
                              (H2 == 0 || ((U2 * H1) % 4 == 0 && NetT::OFF_W2 % 4 == 0 &&
-                                          NetT::OFF_B2 % 4 == 0 && U2 % 4 == 0))),
-                  "parameter slices of a lane must start on Philox blocks");
+                                          NetT::OFF_B2 % 4 == 0 && U2 % 2 == 0))),
+                  "weight slices of a lane must start on Philox blocks, bias slices on pairs");
 
     float w1[U1 * NIN], b1[U1];
     float w2[H2 ? U2 * H1 : 1], b2[U2];
@@ -142,10 +146,10 @@ struct Controller {
             src.template fill_const<NetT::OFF_BO, NO>(bo);
         } else {
             src.fill_aligned(w1, NetT::OFF_W1 + q * U1 * NIN, stage, tid, block);
-            src.fill_aligned(b1, NetT::OFF_B1 + q * U1, stage, tid, block);
+            src.fill_even(b1, NetT::OFF_B1 + q * U1);
             if constexpr (H2) {
                 src.fill_aligned(w2, NetT::OFF_W2 + q * U2 * H1, stage, tid, block);
-                src.fill_aligned(b2, NetT::OFF_B2 + q * U2, stage, tid, block);
+                src.fill_even(b2, NetT::OFF_B2 + q * U2);
             }
             const int r = q & 1;
             src.fill_aligned(wo, NetT::OFF_WO + r * HL, stage, tid, block);

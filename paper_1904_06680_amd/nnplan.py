@@ -19,7 +19,7 @@ NNP_OK, NNP_INFEASIBLE = 0, 1
 NNP_EINVAL, NNP_ENOMEM, NNP_EDEVICE, NNP_EUNSUPPORTED = -1, -2, -3, -4
 FEAT_PAPER, FEAT_SIX, FEAT_EIGHT = 0, 1, 2
 
-EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_rollout",
+EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_batch", "nnp_rollout",
             "nnp_sample_theta", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
             "nnp_version")
 
@@ -80,6 +80,8 @@ def load_library(path: str = LIB):
         "nnp_destroy": (None, [H]),
         "nnp_n_theta": (C.c_int, [H]),
         "nnp_plan": (C.c_int, [H, C.POINTER(nnp_problem), C.POINTER(nnp_result), C.c_void_p]),
+        "nnp_plan_batch": (C.c_int, [H, C.POINTER(nnp_problem), C.c_int, C.POINTER(nnp_result),
+                                     C.c_void_p]),
         "nnp_rollout": (C.c_int, [H, C.POINTER(nnp_problem), C.c_void_p,
                                   C.POINTER(nnp_rollout_out), C.c_void_p]),
         "nnp_sample_theta": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
@@ -114,6 +116,11 @@ def nnp_n_theta(h) -> int:
 
 def nnp_plan(h, problem: nnp_problem, result: nnp_result, stream: int = 0) -> int:
     return load_library().nnp_plan(h, C.byref(problem), C.byref(result), C.c_void_p(stream))
+
+
+def nnp_plan_batch(h, problems, results, stream: int = 0) -> int:
+    """problems: ctypes array of nnp_problem; results: ctypes array of nnp_result (same length)."""
+    return load_library().nnp_plan_batch(h, problems, len(problems), results, C.c_void_p(stream))
 
 
 def nnp_rollout(h, problem: nnp_problem, theta_ptr, out: nnp_rollout_out, stream: int = 0) -> int:
@@ -262,6 +269,36 @@ class Planner:
         self.torch.cuda.synchronize(self._dev())
         del keep
         return out
+
+    def batch_problems(self, scenes_, Ns, seeds, insts=None):
+        """ctypes arrays (problems, results) and keep-alive objects for a batch of scenes."""
+        n = len(scenes_)
+        probs = (nnp_problem * n)()
+        keep = []
+        for i, sc in enumerate(scenes_):
+            pr, k = self.problem(sc, int(Ns[i]), int(seeds[i]), 0 if insts is None else insts[i])
+            probs[i] = pr
+            keep.append(k)
+        return probs, keep
+
+    def plan_batch_async(self, probs, outs: list, stream=None):
+        res = (nnp_result * len(outs))()
+        for i, out in enumerate(outs):
+            for k in ("theta", "controls", "controls_phys", "traj", "cost", "best_index",
+                      "status", "goal_reached"):
+                t = out.get(k)
+                setattr(res[i], k, t.data_ptr() if t is not None else None)
+        _check(nnp_plan_batch(self.h, probs, res, self._stream() if stream is None else stream),
+               self.h)
+        return res
+
+    def plan_batch(self, scenes_, Ns, seeds) -> list:
+        probs, keep = self.batch_problems(scenes_, Ns, seeds)
+        outs = [self.alloc_result(sc.T) for sc in scenes_]
+        self.plan_batch_async(probs, outs)
+        self.torch.cuda.synchronize(self._dev())
+        del keep
+        return outs
 
     def rollout(self, scene, N: int, seed: int = 0, inst: int = 0, theta=None,
                 want_traj: bool = True, want_controls: bool = True) -> dict:

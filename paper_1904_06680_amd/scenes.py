@@ -203,3 +203,48 @@ def random_scene(rng: np.random.Generator, P: int, T: int, box: float = 30.0,
     pts[:, :2] = rng.uniform(-box, box, (P, 2))
     pts[:, 2:] = rng.uniform(-vmax, vmax, (P, 2))
     return Scene(z0, goal, pts, T, name="random")
+
+
+def scene_mixed(rng: np.random.Generator, P: int, T: int, box: float = 65.0,
+                name: str = "mixed") -> Scene:
+    """A C1-style scene with P points: a third of them (rounded to whole obstacles) on moving
+    4.5 x 1.8 m rectangles of 50 points, the rest static, all in [-box, box]^2."""
+    z0 = np.array([0.0, 0.0, rng.uniform(-math.pi, math.pi), rng.uniform(-3.0, 15.0)])
+    dist, bearing = rng.uniform(20.0, 60.0), rng.uniform(-math.pi, math.pi)
+    goal = np.array([dist * math.cos(bearing), dist * math.sin(bearing),
+                     rng.uniform(-math.pi, math.pi), 0.0])
+    n_dyn = int(round(P / 3 / 50))
+    n_static = P - 50 * n_dyn
+    pts = []
+    while len(pts) < n_static:
+        x, y = rng.uniform(-box, box, 2)
+        if not _in_start_footprint(np.array([x]), np.array([y]), z0, C1, 0.5)[0]:
+            pts.append([x, y, 0.0, 0.0])
+    blocks = [np.array(pts, float).reshape(-1, 4)]
+    while len(blocks) < n_dyn + 1:
+        cx, cy = rng.uniform(-box, box, 2)
+        xy = rectangle_outline(cx, cy, rng.uniform(-math.pi, math.pi), 4.5, 1.8, 50)
+        if _in_start_footprint(xy[:, 0], xy[:, 1], z0, C1, 0.5).any():
+            continue
+        blk = np.zeros((50, 4))
+        blk[:, :2] = xy
+        blk[:, 2:] = rng.uniform(-5.0, 5.0, 2)
+        blocks.append(blk)
+    return Scene(z0, goal, np.concatenate(blocks, 0), T, name=name)
+
+
+def batch_c2(seed: int = 0, count: int = 256, n_range=(4096, 65536), p_range=(100, 5000),
+             horizons=(20, 40, 60, 80)):
+    """The batched, uneven workload: `count` independent problems with N log-uniform in
+    n_range, P log-uniform in p_range and T uniform in `horizons`, each a scene_mixed layout.
+    Returns (scenes, Ns, seeds)."""
+    rng = np.random.default_rng([int(seed), 0xC2])
+    scs, Ns, seeds = [], [], []
+    for i in range(count):
+        N = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        P = int(round(math.exp(rng.uniform(math.log(p_range[0]), math.log(p_range[1])))))
+        T = int(horizons[rng.integers(len(horizons))])
+        scs.append(scene_mixed(rng, P, T, name=f"c2-{seed}-{i}"))
+        Ns.append(N)
+        seeds.append(1000 * seed + i)
+    return scs, Ns, seeds

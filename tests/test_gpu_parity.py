@@ -147,20 +147,21 @@ def test_k_layouts_bit_identical():
 
 
 def test_c1_lane_layouts_bit_identical():
-    """The 8-32-32-2 controller split over 4 or 8 lanes per sample gives identical bits."""
+    """The 8-32-32-2 controller split over 4, 8 or 16 lanes per sample gives identical bits."""
     sc = scenes.scene_c1(7)
     N = 1000
-    say(f"lane layouts K=4,8: C1 scene 7, N={N}")
+    say(f"lane layouts K=4,8,16: C1 scene 7, N={N}")
     outs = []
-    for K in (4, 8):
+    for K in (4, 8, 16):
         pl = Planner(scenes.C1, lanes_per_sample=K)
         outs.append(np_out(pl.rollout(sc, N, seed=2)))
         plan = pl.plan(sc, N, seed=2)
         outs[-1]["plan_cost"] = plan["cost"].cpu().numpy()
         outs[-1]["plan_traj"] = plan["traj"].cpu().numpy()
         pl.close()
-    for k in outs[0]:
-        assert np.array_equal(outs[0][k], outs[1][k]), k
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], o[k]), k
 
 
 def test_point_permutation_bit_identical(c1_planner):
