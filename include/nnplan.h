@@ -41,6 +41,7 @@ extern "C" {
 #define NNP_MAX_LAYERS 3
 #define NNP_MAX_T 4096        /* longest horizon accepted                                    */
 #define NNP_MAX_P (1 << 22)   /* most obstacle points accepted                               */
+#define NNP_MAX_BATCH 65535   /* most problems in one nnp_plan_batch call                    */
 
 /* Feature vectors of eq. (3) (Sect. II-E) and the two extended variants:
  * NNP_FEAT_PAPER  5 inputs: [xi_g/dxi, eta_g/deta, wrap(phi_g-phi)/dphi, (v_g-v)/dv, a_prev[0]]
@@ -142,7 +143,8 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
  * The call copies `count` problem descriptors to the device through a pinned staging buffer
  * owned by the handle (it waits for the previous batch's copy before reusing it) and enqueues
  * three kernels. Results are bit-identical to nnp_plan on each problem and to every lane layout.
- * Returns NNP_EINVAL if count < 1 or any problem is invalid (nnp_last_error names it).
+ * Returns NNP_EINVAL if count is outside 1..NNP_MAX_BATCH or any problem is invalid
+ * (nnp_last_error names it).
  * HIP graph capture: the call records one host-to-device copy from the staging buffer and three
  * kernels (no memsets, no host synchronisation). The handle's batch workspace must already be
  * large enough, i.e. an uncaptured call with at least as many problems, samples-times-points and

@@ -896,6 +896,7 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
 {
     if (!h) return NNP_EINVAL;
     if (!probs || !results || count < 1) return fail(h, NNP_EINVAL, "empty batch");
+    if (count > NNP_MAX_BATCH) return fail(h, NNP_EINVAL, "more than NNP_MAX_BATCH problems");
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = hipSetDevice(h->device);
     if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
