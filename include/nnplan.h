@@ -90,6 +90,12 @@ typedef struct nnp_problem {
     uint64_t seed;            /* Philox key                                                     */
     const float *warm_theta;  /* device [n_theta] or NULL: replaces sample 0 (warm start of    */
                               /* the first restart with theta*_{t-1}, Sect. II-E fifth comment) */
+    int32_t n_prop;           /* 0..N: samples 0..n_prop-1 come from the Gaussian proposal      */
+                              /* theta_k = mu_k + exp(log_sigma_k) z_k (z: Box-Muller on Philox  */
+                              /* stream 1, see nnp_sample_gauss); samples n_prop..N-1 are the    */
+                              /* uniform draws 0..N-n_prop-1 of stream 0. 0 = plain sampler.     */
+    const float *prop_mu;        /* device [n_theta] proposal mean (may be NULL if n_prop = 0)   */
+    const float *prop_log_sigma; /* device [n_theta] proposal log standard deviation             */
 } nnp_problem;
 
 /* Outputs of nnp_plan: caller-owned device buffers; any member may be NULL to skip it. */
@@ -166,6 +172,16 @@ int nnp_rollout(nnp_handle *h, const nnp_problem *p, const float *theta, nnp_rol
  * current HIP device. */
 int nnp_sample_theta(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
                      float *out, void *hip_stream);
+
+/* The proposal draws of nnp_plan (samples with index < n_prop) for Philox sample words
+ * i0..i0+N-1 into device out[N][n_theta]: theta_k = mu_k + exp(log_sigma_k) z_k, rounded once
+ * (fused multiply-add), with z the Box-Muller normals of Philox4x32-10(counter = (k / 4, i, 1,
+ * inst), key = (seed low 32, seed high 32)): words (0, 1) serve k mod 4 in {0, 1}, words (2, 3)
+ * serve {2, 3}; u = (m + 1/2) 2^-23 with m the top 23 bits of a word; z = sqrt(-2 ln u_a)
+ * cos(2 pi u_b) for even k, sin for odd k. mu and log_sigma are device [n_theta]. Runs on the
+ * current HIP device. Bit-identical to the draws inside nnp_plan. */
+int nnp_sample_gauss(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
+                     const float *mu, const float *log_sigma, float *out, void *hip_stream);
 
 /* Text of the handle's last error ("" if none). With h == NULL: the last nnp_create failure. */
 const char *nnp_last_error(const nnp_handle *h);

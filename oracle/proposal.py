@@ -33,7 +33,8 @@ Adam (Kingma and Ba, 2015) with bias correction: m = b1 m + (1 - b1) g, v = b2 v
 w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
 Gaussian draws: theta_k = mu_k + exp(s_k) z_k with z from the Box-Muller transform (Box and
-Muller, 1958) of two uniforms u = (m + 1/2) 2^-24 (m the top 24 bits of a Philox4x32-10 word):
+Muller, 1958) of two uniforms u = (m + 1/2) 2^-23 (m the top 23 bits of a Philox4x32-10 word, so
+that u is an exact binary32 value):
 parameter k of sample i uses block (k >> 2, i, 1, inst) under key = seed, words (0, 1) for
 k & 3 in {0, 1} and words (2, 3) for k & 3 in {2, 3}; z = sqrt(-2 ln u_a) cos(2 pi u_b) for even
 k, the sine for odd k.
@@ -207,8 +208,8 @@ def normals(seed: int, inst: int, i0: int, n: int, n_theta: int) -> np.ndarray:
             w = philox((b, i0 + r, 1, inst), key)
             for k in range(4 * b, min(4 * b + 4, n_theta)):
                 pa = 2 * ((k & 3) >> 1)
-                ua = ((w[pa] >> 8) + 0.5) * 2.0 ** -24
-                ub = ((w[pa + 1] >> 8) + 0.5) * 2.0 ** -24
+                ua = ((w[pa] >> 9) + 0.5) * 2.0 ** -23
+                ub = ((w[pa + 1] >> 9) + 0.5) * 2.0 ** -23
                 rad = math.sqrt(-2.0 * math.log(ua))
                 ang = 2.0 * math.pi * ub
                 out[r, k] = rad * (math.cos(ang) if k % 2 == 0 else math.sin(ang))
@@ -220,3 +221,26 @@ def sample(mu, log_sigma, seed: int, inst: int, i0: int, n: int) -> np.ndarray:
     mu = np.asarray(mu, np.float64)
     z = normals(seed, inst, i0, n, len(mu))
     return mu[None, :] + np.exp(np.asarray(log_sigma, np.float64))[None, :] * z
+
+
+# ------------------------------------------------------------------------------------------------
+# Flat parameter vector: W1 [256][72], b1, W2 [256][256], b2, W3 [2 n_theta][256], b3
+# ------------------------------------------------------------------------------------------------
+ORDER = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def flatten(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], np.float64).ravel() for k in ORDER])
+
+
+def unflatten(vec, n_theta: int, enc_dim: int = ENC_DIM, hidden: int = HIDDEN) -> dict:
+    shapes = {"W1": (hidden, enc_dim), "b1": (hidden,), "W2": (hidden, hidden), "b2": (hidden,),
+              "W3": (2 * n_theta, hidden), "b3": (2 * n_theta,)}
+    vec = np.asarray(vec, np.float64)
+    out, o = {}, 0
+    for k in ORDER:
+        n = int(np.prod(shapes[k]))
+        out[k] = vec[o:o + n].reshape(shapes[k]).copy()
+        o += n
+    assert o == len(vec), (o, len(vec))
+    return out

@@ -1,4 +1,5 @@
-"""Build the HIP library ``libnnplan.so`` (gfx950) in the package directory with hipcc.
+"""Build the HIP library ``libnnplan.so`` (gfx950: the planner and the proposal network) in the
+package directory with hipcc.
 
 All device code is compiled without packed-FP32 instructions and without floating-point
 contraction; every fused multiply-add in the kernels is written out explicitly.
@@ -11,7 +12,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "nnplan.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("nnplan.hip", "proposal.hip")]
 LIB = os.path.join(HERE, "libnnplan.so")
 
 HIPCC_FLAGS = [
@@ -31,7 +32,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

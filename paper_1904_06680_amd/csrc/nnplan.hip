@@ -53,6 +53,8 @@ struct RolloutArgs {
     float *min_margin, *traj, *controls;
     const float4 *obst;              // raw points [P][4] (batched extrapolation)
     int P;
+    const float *mu, *log_sigma;     // Gaussian proposal for samples [0, n_prop)
+    int n_prop;
 };
 
 struct ReplayOut {
@@ -116,8 +118,19 @@ __device__ __forceinline__ ThetaSource make_source(const RolloutArgs &a, int sam
     src.inst = a.inst;
     src.sample = (uint32_t)sample;
     src.explicit_theta = nullptr;
-    if (a.theta) src.explicit_theta = a.theta + (size_t)sample * NetT::NTHETA;
-    else if (a.warm_theta && sample == 0) src.explicit_theta = a.warm_theta;
+    src.mu = nullptr;
+    src.log_sigma = nullptr;
+    src.n_theta = NetT::NTHETA;
+    if (a.theta) {
+        src.explicit_theta = a.theta + (size_t)sample * NetT::NTHETA;
+    } else if (a.warm_theta && sample == 0) {
+        src.explicit_theta = a.warm_theta;
+    } else if (sample < a.n_prop) {
+        src.mu = a.mu;                 // proposal draws: stream 1, own sample index
+        src.log_sigma = a.log_sigma;
+    } else {
+        src.sample = (uint32_t)(sample - a.n_prop);   // uniform draws: stream 0 from index 0
+    }
     return src;
 }
 
@@ -465,6 +478,8 @@ __global__ __launch_bounds__(BLOCK) void replay_batch_kernel(const RolloutArgs *
 
 __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,
                                                       uint32_t N, uint32_t nt,
+                                                      const float *__restrict__ mu,
+                                                      const float *__restrict__ log_sigma,
                                                       float *__restrict__ out)
 {
     const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
@@ -472,6 +487,9 @@ __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t in
     const uint32_t i = (uint32_t)(gid / nt), k = (uint32_t)(gid % nt);
     ThetaSource src;
     src.explicit_theta = nullptr;
+    src.mu = mu;
+    src.log_sigma = log_sigma;
+    src.n_theta = (int)nt;
     src.key = key;
     src.inst = inst;
     src.sample = i0 + i;
@@ -702,6 +720,9 @@ int check_problem(nnp_handle *h, const nnp_problem *p)
         for (int i = 0; i < 2; ++i)
             if (!(fabsf(p->a_prev[i]) <= 1.0f))
                 return fail(h, NNP_EINVAL, "a_prev must be finite and in [-1, 1]");
+    if (p->n_prop < 0 || p->n_prop > p->N) return fail(h, NNP_EINVAL, "n_prop must be in [0, N]");
+    if (p->n_prop > 0 && (!p->prop_mu || !p->prop_log_sigma))
+        return fail(h, NNP_EINVAL, "prop_mu / prop_log_sigma are null with n_prop > 0");
     return NNP_OK;
 }
 
@@ -734,6 +755,9 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
     a.warm_theta = p->warm_theta;
     a.obst = reinterpret_cast<const float4 *>(p->obst);
     a.P = p->P;
+    a.n_prop = p->n_prop;
+    a.mu = p->n_prop > 0 ? p->prop_mu : nullptr;
+    a.log_sigma = p->n_prop > 0 ? p->prop_log_sigma : nullptr;
     return NNP_OK;
 }
 
@@ -1031,7 +1055,19 @@ int nnp_sample_theta(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint
     if (n >= (1ll << 40)) return NNP_EINVAL;
     PhiloxKey key = {(uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32)};
     hipLaunchKernelGGL(theta_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                       (hipStream_t)hip_stream, key, inst, i0, N, n_theta, out);
+                       (hipStream_t)hip_stream, key, inst, i0, N, n_theta, nullptr, nullptr, out);
+    return hipGetLastError() == hipSuccess ? NNP_OK : NNP_EDEVICE;
+}
+
+int nnp_sample_gauss(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
+                     const float *mu, const float *log_sigma, float *out, void *hip_stream)
+{
+    if (!out || !mu || !log_sigma || N == 0 || n_theta == 0) return NNP_EINVAL;
+    const long long n = (long long)N * n_theta;
+    if (n >= (1ll << 40)) return NNP_EINVAL;
+    PhiloxKey key = {(uint32_t)(seed & 0xffffffffull), (uint32_t)(seed >> 32)};
+    hipLaunchKernelGGL(theta_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       (hipStream_t)hip_stream, key, inst, i0, N, n_theta, mu, log_sigma, out);
     return hipGetLastError() == hipSuccess ? NNP_OK : NNP_EDEVICE;
 }
 

@@ -46,25 +46,74 @@ __device__ __forceinline__ float theta_from_word(uint32_t w)
     return (float)(2 * m + 1 - 16777216) * 5.9604644775390625e-8f;
 }
 
-__device__ __forceinline__ uint32_t word_of(uint4 w, int j)
+// Standard normal pair from two Philox words by the Box-Muller transform (G. E. P. Box and
+// M. E. Muller, 1958): u = (m + 1/2) 2^-23 with m the top 23 bits of a word, so u and 2u are exact
+// floats in (0, 1) and (0, 2); z0 = sqrt(-2 ln u_a) cos(2 pi u_b), z1 = the sine.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float &z0, float &z1)
 {
-    return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w;
+    const float ua = (float)(2 * (int)(wa >> 9) + 1) * 5.9604644775390625e-8f;     // 2^-24
+    const float two_ub = (float)(2 * (int)(wb >> 9) + 1) * 1.1920928955078125e-7f;  // 2^-23
+    const float r = sqrtf(-2.0f * logf(ua));
+    float sn, cs;
+    sincospif(two_ub, &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
 }
 
-// Counter layout: (k / 4, sample, stream, inst); stream 0 is the uniform parameter draw.
+// Counter layout: (k / 4, sample, stream, inst). Stream 0 is the uniform parameter draw; stream 1
+// the Gaussian proposal theta_k = mu_k + exp(s_k) z_k, whose normals come from block k / 4: words
+// (0, 1) for k mod 4 in {0, 1}, words (2, 3) for {2, 3}, cosine for even k, sine for odd k.
 struct ThetaSource {
     const float *explicit_theta;   // row of this sample in an explicit [N][n_theta] array, or null
+    const float *mu, *log_sigma;   // Gaussian proposal of this sample's problem, or null (uniform)
+    int n_theta;                   // length of mu / log_sigma
     PhiloxKey key;
-    uint32_t sample, inst;
+    uint32_t sample, inst;         // Philox sample word (index within the sample's own stream)
 
-    __device__ __forceinline__ uint4 block4(int c) const
+    __device__ __forceinline__ uint4 block4(int c, uint32_t stream) const
     {
-        return philox4x32_10(make_uint4((uint32_t)c, sample, 0u, inst), key);
+        return philox4x32_10(make_uint4((uint32_t)c, sample, stream, inst), key);
+    }
+
+    __device__ __forceinline__ float gauss(int k, float z) const
+    {
+        return k < n_theta ? fmaf(expf(log_sigma[k]), z, mu[k]) : 0.0f;
+    }
+
+    // theta[k], theta[k + 1] for even k.
+    __device__ __forceinline__ float2 pair(int k) const
+    {
+        if (!mu) {
+            const uint4 w = block4(k >> 2, 0u);
+            return (k & 2) ? make_float2(theta_from_word(w.z), theta_from_word(w.w))
+                           : make_float2(theta_from_word(w.x), theta_from_word(w.y));
+        }
+        const uint4 w = block4(k >> 2, 1u);
+        float z0, z1;
+        if (k & 2) box_muller(w.z, w.w, z0, z1);
+        else box_muller(w.x, w.y, z0, z1);
+        return make_float2(gauss(k, z0), gauss(k + 1, z1));
+    }
+
+    // theta[4c .. 4c + 3].
+    __device__ __forceinline__ float4 value4(int c) const
+    {
+        if (!mu) {
+            const uint4 w = block4(c, 0u);
+            return make_float4(theta_from_word(w.x), theta_from_word(w.y), theta_from_word(w.z),
+                               theta_from_word(w.w));
+        }
+        const uint4 w = block4(c, 1u);
+        float z0, z1, z2, z3;
+        box_muller(w.x, w.y, z0, z1);
+        box_muller(w.z, w.w, z2, z3);
+        return make_float4(gauss(4 * c, z0), gauss(4 * c + 1, z1), gauss(4 * c + 2, z2),
+                           gauss(4 * c + 3, z3));
     }
 
     // dst[e] = theta[base + e] for a base that is a multiple of 4. Long slices are generated
     // in chunks of STAGE values through a per-lane LDS staging area (stage[e * BLOCK + tid]) so
-    // that the Philox loop can stay rolled while every register of dst is written with a
+    // that the generator loop can stay rolled while every register of dst is written with a
     // compile-time index.
     static constexpr int STAGE = 32;
 
@@ -80,11 +129,11 @@ struct ThetaSource {
         if constexpr (COUNT <= STAGE) {
 #pragma unroll
             for (int c = 0; c < (COUNT + 3) / 4; ++c) {
-                const uint4 w = block4((base >> 2) + c);
-                if (4 * c + 0 < COUNT) dst[4 * c + 0] = theta_from_word(w.x);
-                if (4 * c + 1 < COUNT) dst[4 * c + 1] = theta_from_word(w.y);
-                if (4 * c + 2 < COUNT) dst[4 * c + 2] = theta_from_word(w.z);
-                if (4 * c + 3 < COUNT) dst[4 * c + 3] = theta_from_word(w.w);
+                const float4 w = value4((base >> 2) + c);
+                if (4 * c + 0 < COUNT) dst[4 * c + 0] = w.x;
+                if (4 * c + 1 < COUNT) dst[4 * c + 1] = w.y;
+                if (4 * c + 2 < COUNT) dst[4 * c + 2] = w.z;
+                if (4 * c + 3 < COUNT) dst[4 * c + 3] = w.w;
             }
         } else {
             static_assert(COUNT % 4 == 0, "aligned slices come in whole Philox blocks");
@@ -94,11 +143,11 @@ struct ThetaSource {
                 const int len = ch + 1 < NCH ? STAGE : COUNT - (NCH - 1) * STAGE;
 #pragma unroll 1
                 for (int c = 0; c < len / 4; ++c) {
-                    const uint4 w = block4((base >> 2) + ch * (STAGE / 4) + c);
-                    stage[(4 * c + 0) * block + tid] = theta_from_word(w.x);
-                    stage[(4 * c + 1) * block + tid] = theta_from_word(w.y);
-                    stage[(4 * c + 2) * block + tid] = theta_from_word(w.z);
-                    stage[(4 * c + 3) * block + tid] = theta_from_word(w.w);
+                    const float4 w = value4((base >> 2) + ch * (STAGE / 4) + c);
+                    stage[(4 * c + 0) * block + tid] = w.x;
+                    stage[(4 * c + 1) * block + tid] = w.y;
+                    stage[(4 * c + 2) * block + tid] = w.z;
+                    stage[(4 * c + 3) * block + tid] = w.w;
                 }
 #pragma unroll
                 for (int e = 0; e < STAGE; ++e)
@@ -120,11 +169,9 @@ struct ThetaSource {
         }
 #pragma unroll
         for (int e = 0; e < COUNT; e += 2) {
-            const int k = base + e;
-            const uint4 w = block4(k >> 2);
-            const bool hi = (k & 2) != 0;
-            dst[e] = theta_from_word(hi ? w.z : w.x);
-            dst[e + 1] = theta_from_word(hi ? w.w : w.y);
+            const float2 w = pair(base + e);
+            dst[e] = w.x;
+            dst[e + 1] = w.y;
         }
     }
 
@@ -140,11 +187,12 @@ struct ThetaSource {
         constexpr int c0 = BASE >> 2, c1 = (BASE + COUNT - 1) >> 2;
 #pragma unroll
         for (int c = c0; c <= c1; ++c) {
-            const uint4 w = block4(c);
+            const float4 w = value4(c);
+            const float v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int e = 4 * c + j - BASE;
-                if (e >= 0 && e < COUNT) dst[e] = theta_from_word(word_of(w, j));
+                if (e >= 0 && e < COUNT) dst[e] = v[j];
             }
         }
     }
@@ -153,7 +201,8 @@ struct ThetaSource {
     __device__ __forceinline__ float one(int k) const
     {
         if (explicit_theta) return explicit_theta[k];
-        return theta_from_word(word_of(block4(k >> 2), k & 3));
+        const float2 w = pair(k & ~1);
+        return (k & 1) ? w.y : w.x;
     }
 };
 

@@ -20,7 +20,7 @@ NNP_EINVAL, NNP_ENOMEM, NNP_EDEVICE, NNP_EUNSUPPORTED = -1, -2, -3, -4
 FEAT_PAPER, FEAT_SIX, FEAT_EIGHT = 0, 1, 2
 
 EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_batch", "nnp_rollout",
-            "nnp_sample_theta", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
+            "nnp_sample_theta", "nnp_sample_gauss", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
             "nnp_version")
 
 
@@ -44,6 +44,7 @@ class nnp_problem(C.Structure):
         ("z0", C.c_float * 4), ("goal", C.c_float * 4), ("a_prev", C.POINTER(C.c_float)),
         ("obst", C.c_void_p), ("P", C.c_int32), ("N", C.c_int32), ("T", C.c_int32),
         ("inst", C.c_uint32), ("seed", C.c_uint64), ("warm_theta", C.c_void_p),
+        ("n_prop", C.c_int32), ("prop_mu", C.c_void_p), ("prop_log_sigma", C.c_void_p),
     ]
 
 
@@ -86,6 +87,9 @@ def load_library(path: str = LIB):
                                   C.POINTER(nnp_rollout_out), C.c_void_p]),
         "nnp_sample_theta": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                        C.c_uint32, C.c_void_p, C.c_void_p]),
+        "nnp_sample_gauss": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                       C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
         "nnp_last_error": (C.c_char_p, [H]),
         "nnp_set_timing": (C.c_int, [H, C.c_int]),
         "nnp_kernel_time": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
@@ -131,6 +135,13 @@ def nnp_rollout(h, problem: nnp_problem, theta_ptr, out: nnp_rollout_out, stream
 def nnp_sample_theta(seed: int, inst: int, i0: int, N: int, n_theta: int, out_ptr: int,
                      stream: int = 0) -> int:
     return load_library().nnp_sample_theta(seed, inst, i0, N, n_theta, C.c_void_p(out_ptr),
+                                           C.c_void_p(stream))
+
+
+def nnp_sample_gauss(seed: int, inst: int, i0: int, N: int, n_theta: int, mu_ptr: int,
+                     log_sigma_ptr: int, out_ptr: int, stream: int = 0) -> int:
+    return load_library().nnp_sample_gauss(seed, inst, i0, N, n_theta, C.c_void_p(mu_ptr),
+                                           C.c_void_p(log_sigma_ptr), C.c_void_p(out_ptr),
                                            C.c_void_p(stream))
 
 
@@ -214,8 +225,9 @@ class Planner:
         return self.torch.cuda.current_stream(self._dev()).cuda_stream
 
     def problem(self, scene, N: int, seed: int = 0, inst: int = 0, obst=None,
-                warm_theta=None) -> tuple:
-        """nnp_problem for a scene; returns (problem, keep-alive tuple)."""
+                warm_theta=None, proposal=None) -> tuple:
+        """nnp_problem for a scene; returns (problem, keep-alive tuple). `proposal` = (mu,
+        log_sigma, n_prop) draws samples 0..n_prop-1 from that Gaussian (device tensors)."""
         torch = self.torch
         pr = nnp_problem()
         for i in range(4):
@@ -241,6 +253,12 @@ class Planner:
         if warm_theta is not None:
             keep.append(warm_theta)
             pr.warm_theta = warm_theta.data_ptr()
+        if proposal is not None:
+            mu, ls, n_prop = proposal
+            keep += [mu, ls]
+            pr.prop_mu = mu.data_ptr()
+            pr.prop_log_sigma = ls.data_ptr()
+            pr.n_prop = int(n_prop)
         return pr, keep
 
     def plan_async(self, pr: nnp_problem, out: dict, stream=None):
@@ -262,8 +280,9 @@ class Planner:
                     status=torch.empty(1, dtype=torch.int32, device=d),
                     goal_reached=torch.empty(1, dtype=torch.int32, device=d))
 
-    def plan(self, scene, N: int, seed: int = 0, inst: int = 0, warm_theta=None) -> dict:
-        pr, keep = self.problem(scene, N, seed, inst, warm_theta=warm_theta)
+    def plan(self, scene, N: int, seed: int = 0, inst: int = 0, warm_theta=None,
+             proposal=None) -> dict:
+        pr, keep = self.problem(scene, N, seed, inst, warm_theta=warm_theta, proposal=proposal)
         out = self.alloc_result(scene.T)
         self.plan_async(pr, out)
         self.torch.cuda.synchronize(self._dev())
@@ -301,9 +320,9 @@ class Planner:
         return outs
 
     def rollout(self, scene, N: int, seed: int = 0, inst: int = 0, theta=None,
-                want_traj: bool = True, want_controls: bool = True) -> dict:
+                want_traj: bool = True, want_controls: bool = True, proposal=None) -> dict:
         torch, d = self.torch, self._dev()
-        pr, keep = self.problem(scene, N, seed, inst)
+        pr, keep = self.problem(scene, N, seed, inst, proposal=proposal)
         T = scene.T
         out = dict(cost=torch.empty(N, dtype=torch.float32, device=d),
                    collided=torch.empty(N, dtype=torch.int32, device=d),
@@ -333,6 +352,13 @@ class Planner:
         out = torch.empty(N, self.n_theta, dtype=torch.float32, device=self._dev())
         _check(nnp_sample_theta(seed, inst, i0, N, self.n_theta, out.data_ptr(), self._stream()))
         torch.cuda.synchronize(self._dev())
+        return out
+
+    def sample_gauss(self, mu, log_sigma, N: int, seed: int = 0, inst: int = 0, i0: int = 0):
+        torch = self.torch
+        out = torch.empty(N, self.n_theta, dtype=torch.float32, device=self._dev())
+        _check(nnp_sample_gauss(seed, inst, i0, N, self.n_theta, mu.data_ptr(),
+                                log_sigma.data_ptr(), out.data_ptr(), self._stream()))
         return out
 
     def set_timing(self, enable: bool = True):

@@ -4,23 +4,28 @@ import ctypes as C
 import math
 import os
 import re
+import subprocess
 
 import pytest
 
 from conftest import ROOT
-from paper_1904_06680_amd import nnplan, scenes
+from paper_1904_06680_amd import nnplan, proposal, scenes
 
-HEADER = os.path.join(ROOT, "include", "nnplan.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nnplan.h", "nnproposal.h")]
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nnp_[a-z_0-9]+)\s*\(", text)))
+def declared_functions(header=None):
+    names = set()
+    for h in ([header] if header else HEADERS):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(nnp_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_surface():
-    assert declared_functions() == sorted(nnplan.EXPORTED)
+    assert declared_functions(HEADERS[0]) == sorted(nnplan.EXPORTED)
+    assert declared_functions(HEADERS[1]) == sorted(proposal.EXPORTED)
 
 
 def test_library_exports_every_declared_symbol():
@@ -30,12 +35,33 @@ def test_library_exports_every_declared_symbol():
     assert nnplan.nnp_version().startswith("nnplan")
 
 
-def test_struct_layouts_match_header_sizes():
-    # Field-by-field mirror of the header structs; sizes follow the C layout rules.
-    assert C.sizeof(nnplan.nnp_model) == 4 * 12 + 4 + 16 + 4 + 4 * 6 + 4 * 4 + 4
-    assert C.sizeof(nnplan.nnp_problem) == 16 + 16 + 8 + 8 + 4 * 4 + 8 + 8
-    assert C.sizeof(nnplan.nnp_result) == 8 * 8
-    assert C.sizeof(nnplan.nnp_rollout_out) == 8 * 6
+def _c_layout(tmp_path, structs):
+    """sizeof and offsetof of every field, as the C compiler lays out the header's structs."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nnproposal.h"',
+             'int main(void){']
+    for name, cls in structs:
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = [("nnp_model", nnplan.nnp_model), ("nnp_problem", nnplan.nnp_problem),
+               ("nnp_result", nnplan.nnp_result), ("nnp_rollout_out", nnplan.nnp_rollout_out),
+               ("nnp_proposal_config", proposal.nnp_proposal_config)]
+    lay = _c_layout(tmp_path, structs)
+    for name, cls in structs:
+        assert C.sizeof(cls) == lay[name], name
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
 
 
 def _create(preset, **over):

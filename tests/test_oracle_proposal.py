@@ -215,7 +215,7 @@ def test_normals_use_stream_one_words():
     seed, inst = 0x1234_5678_9ABC, 9
     z = P.normals(seed, inst, 5, 1, 8)[0]
     w = oracle.philox((1, 5, 1, inst), (seed & 0xFFFFFFFF, seed >> 32))
-    ua, ub = ((w[2] >> 8) + 0.5) / 2 ** 24, ((w[3] >> 8) + 0.5) / 2 ** 24
+    ua, ub = ((w[2] >> 9) + 0.5) / 2 ** 23, ((w[3] >> 9) + 0.5) / 2 ** 23
     r = math.sqrt(-2 * math.log(ua))
     assert z[6] == pytest.approx(r * math.cos(2 * math.pi * ub), abs=1e-15)
     assert z[7] == pytest.approx(r * math.sin(2 * math.pi * ub), abs=1e-15)
