@@ -18,6 +18,7 @@ constexpr int ENC_PAD = 128;          // encoding padded with zero columns to a 
 constexpr int HID = NNP_PROP_HIDDEN;
 constexpr int NEAR = NNP_PROP_NEAR;
 constexpr int ROWS = 128;             // batch padding (GEMM tile rows)
+constexpr int COL_CHUNKS = 16;        // row chunks of the bias-gradient column sums
 constexpr float PI_F = 3.14159265358979f;
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -47,6 +48,7 @@ struct GemmArgs {
     int ldc;
     uint16_t *Cq;
     int ldcq;
+    float *partial;     // split-K: per-slice sums [gridDim.z][M][N] instead of the epilogue
 };
 
 // Global -> registers for one K step: 512 chunks of 8 bf16 per operand tile, two per thread.
@@ -96,7 +98,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int nk = g.K / TK;
+    // K range of this slice (gridDim.z slices; one slice without split-K)
+    const int nkt = g.K / TK;
+    const int kt0 = (int)((long long)blockIdx.z * nkt / gridDim.z);
+    const int kt1 = (int)((long long)(blockIdx.z + 1) * nkt / gridDim.z);
 
     f32x16 acc[2][2];
 #pragma unroll
@@ -107,16 +112,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     uint4 ra[2], rb[2];
-    load_tile<LA>(g.A, g.lda, m0, 0, tid, ra);
-    load_tile<LB>(g.B, g.ldb, n0, 0, tid, rb);
+    load_tile<LA>(g.A, g.lda, m0, kt0 * TK, tid, ra);
+    load_tile<LB>(g.B, g.ldb, n0, kt0 * TK, tid, rb);
     store_tile<LA>(As[0], tid, ra);
     store_tile<LB>(Bs[0], tid, rb);
     __syncthreads();
 
     const int lr = lane & 31, lk = (lane >> 5) * 8;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) {
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int buf = (kt - kt0) & 1;
+        if (kt + 1 < kt1) {
             load_tile<LA>(g.A, g.lda, m0, (kt + 1) * TK, tid, ra);
             load_tile<LB>(g.B, g.ldb, n0, (kt + 1) * TK, tid, rb);
         }
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0,
                                                                        0, 0);
         }
-        if (kt + 1 < nk) {
+        if (kt + 1 < kt1) {
             store_tile<LA>(As[buf ^ 1], tid, ra);
             store_tile<LB>(Bs[buf ^ 1], tid, rb);
         }
@@ -145,6 +150,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
 
     // Accumulator layout of the 32 x 32 block: lane l holds column l % 32 and rows
     // 8 (r / 4) + 4 (l / 32) + r % 4 for r = 0..15.
+    if (g.partial) {
+        float *P = g.partial + (size_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = n0 + wn * 64 + j * 32 + lr;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    P[(size_t)row * g.N + col] = acc[i][j][r];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -162,9 +182,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
         }
 }
 
-int launch_gemm(int la, int lb, int epi, const GemmArgs &g, hipStream_t s)
+// Split-K finish: C[m][n] = sum over slices z = 0..S-1, in slice order (deterministic).
+__global__ void splitk_reduce_kernel(const float *__restrict__ partial, int S, int M, int N,
+                                     float *__restrict__ C, int ldc)
 {
-    const dim3 grid(g.N / TN, g.M / TM), block(256);
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (size_t)M * N) return;
+    float acc = 0.0f;
+    for (int z = 0; z < S; ++z) acc += partial[(size_t)z * M * N + i];
+    C[(i / N) * ldc + i % N] = acc;
+}
+
+int launch_gemm(int la, int lb, int epi, const GemmArgs &g, hipStream_t s, int splits = 1)
+{
+    const dim3 grid(g.N / TN, g.M / TM, splits), block(256);
 #define NNP_GEMM_CASE(LA, LB, E)                                                          \
     if (la == LA && lb == LB && epi == E) {                                               \
         hipLaunchKernelGGL((gemm_kernel<LA, LB, E>), grid, block, 0, s, g);             \
@@ -331,18 +362,32 @@ __global__ void loss_final_kernel(const float *__restrict__ partial, int B, floa
     *loss = (float)(s / B);
 }
 
-// out[n] = sum over rows b < B of X[b][n], in row order (deterministic).
-__global__ void colsum_kernel(const float *__restrict__ X, int ld, int B, int N,
-                              float *__restrict__ out)
+// Column sums over rows b < B: chunk c = blockIdx.y of gridDim.y sums its rows in row order into
+// part[c][n]; the final pass adds the chunks in order (deterministic).
+__global__ void colsum_partial_kernel(const float *__restrict__ X, int ld, int B, int N,
+                                      float *__restrict__ part)
+{
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    const int c = blockIdx.y, C = gridDim.y;
+    const int b0 = (int)((long long)c * B / C), b1 = (int)((long long)(c + 1) * B / C);
+    float s = 0.0f;
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += X[(size_t)b * ld + n];
+    part[(size_t)c * N + n] = s;
+}
+
+__global__ void colsum_final_kernel(const float *__restrict__ part, int chunks, int N,
+                                    float *__restrict__ out)
 {
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += X[(size_t)b * ld + n];
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
     out[n] = s;
 }
 
-// Adam over the internal (padded) parameter layout; refreshes the bfloat16 weight copies.
+// Adam over the internal (padded) parameter layout (the bfloat16 copies are refreshed after).
 __global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
                             const float *__restrict__ g, int n, float lr, float c1, float c2)
 {
@@ -416,6 +461,9 @@ struct nnp_proposal {
              *da1q = nullptr;
     float *a1 = nullptr, *a2 = nullptr, *y = nullptr, *dyf = nullptr, *da2 = nullptr,
           *da1 = nullptr, *partial = nullptr, *loss_tmp = nullptr;
+    float *splitk = nullptr;                  // split-K slices of the weight gradients
+    size_t splitk_floats = 0;
+    float *colpart = nullptr;                 // column-sum partials [COL_CHUNKS][ny_pad]
     // encoding descriptors
     EncProblem *d_enc = nullptr, *h_enc = nullptr;
     int enc_cap = 0;
@@ -449,10 +497,38 @@ int gemm(nnp_proposal *q, int la, int lb, int epi, int M, int N, int K, const ui
          const uint16_t *B, int ldb, const float *bias, const float *mask, int ldm, float *C,
          int ldc, uint16_t *Cq, int ldcq, hipStream_t s)
 {
-    GemmArgs g{A, B, lda, ldb, M, N, K, bias, mask, ldm, C, ldc, Cq, ldcq};
+    GemmArgs g{A, B, lda, ldb, M, N, K, bias, mask, ldm, C, ldc, Cq, ldcq, nullptr};
     const int rc = launch_gemm(la, lb, epi, g, s);
     if (rc) return pfail(q, rc, "GEMM launch failed");
     return NNP_OK;
+}
+
+// Weight gradient C = A^T-style product with a long K (the batch): split K over enough slices to
+// give the GPU about 512 workgroups, then reduce the slices in order.
+int gemm_splitk(nnp_proposal *q, int la, int lb, int M, int N, int K, const uint16_t *A, int lda,
+                const uint16_t *B, int ldb, float *C, int ldc, hipStream_t s)
+{
+    const int tiles = (M / TM) * (N / TN), nkt = K / TK;
+    int S = std::min(std::min((512 + tiles - 1) / tiles, nkt), 32);
+    while (S > 1 && (size_t)S * M * N > q->splitk_floats) --S;
+    if (S <= 1) return gemm(q, la, lb, 0, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, ldc,
+                            nullptr, 0, s);
+    GemmArgs g{A, B, lda, ldb, M, N, K, nullptr, nullptr, 0, nullptr, 0, nullptr, 0, q->splitk};
+    int rc = launch_gemm(la, lb, 0, g, s, S);
+    if (rc) return pfail(q, rc, "GEMM launch failed");
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks((size_t)M * N)), dim3(256), 0, s,
+                       q->splitk, S, M, N, C, ldc);
+    return NNP_OK;
+}
+
+// Column sums over the first B rows in two deterministic passes: COL_CHUNKS row chunks, then the
+// chunk partials in order.
+void colsum(nnp_proposal *q, const float *X, int ld, int B, int N, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks(N), COL_CHUNKS), dim3(256), 0, s, X, ld,
+                       B, N, q->colpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks(N)), dim3(256), 0, s, q->colpart,
+                       COL_CHUNKS, N, out);
 }
 
 // Forward pass of B rows (padded to Bp) from enc into the workspace.
@@ -481,24 +557,20 @@ int backward_ws(nnp_proposal *q, const float *ts, int B, int Bp, float *loss, hi
         hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, q->partial, B, loss);
     float *g = q->grads;
     // layer 3: dW3 = dy^T h2q, db3 = colsum(dy), dh2 = dy W3 -> da2 = dh2 * [a2 > 0]
-    int rc = gemm(q, 1, 1, 0, L.ny_pad, HID, Bp, q->dyq, L.ny_pad, q->h2q, HID, nullptr, nullptr,
-                  0, g + L.oW3, HID, nullptr, 0, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(L.ny_pad)), dim3(256), 0, s, q->dyf, L.ny_pad, B,
-                       L.ny_pad, g + L.ob3);
+    int rc = gemm_splitk(q, 1, 1, L.ny_pad, HID, Bp, q->dyq, L.ny_pad, q->h2q, HID, g + L.oW3,
+                         HID, s);
+    colsum(q, q->dyf, L.ny_pad, B, L.ny_pad, g + L.ob3, s);
     if (!rc) rc = gemm(q, 0, 1, 2, Bp, HID, L.ny_pad, q->dyq, L.ny_pad, q->wq + q->qW3, HID,
                        nullptr, q->a2, HID, q->da2, HID, q->da2q, HID, s);
     // layer 2
-    if (!rc) rc = gemm(q, 1, 1, 0, HID, HID, Bp, q->da2q, HID, q->h1q, HID, nullptr, nullptr, 0,
-                       g + L.oW2, HID, nullptr, 0, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(HID)), dim3(256), 0, s, q->da2, HID, B, HID,
-                       g + L.ob2);
+    if (!rc) rc = gemm_splitk(q, 1, 1, HID, HID, Bp, q->da2q, HID, q->h1q, HID, g + L.oW2, HID, s);
+    colsum(q, q->da2, HID, B, HID, g + L.ob2, s);
     if (!rc) rc = gemm(q, 0, 1, 2, Bp, HID, HID, q->da2q, HID, q->wq + q->qW2, HID, nullptr,
                        q->a1, HID, q->da1, HID, q->da1q, HID, s);
     // layer 1
-    if (!rc) rc = gemm(q, 1, 1, 0, HID, ENC_PAD, Bp, q->da1q, HID, q->xq, ENC_PAD, nullptr,
-                       nullptr, 0, g + L.oW1, ENC_PAD, nullptr, 0, s);
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks(HID)), dim3(256), 0, s, q->da1, HID, B, HID,
-                       g + L.ob1);
+    if (!rc) rc = gemm_splitk(q, 1, 1, HID, ENC_PAD, Bp, q->da1q, HID, q->xq, ENC_PAD, g + L.oW1,
+                              ENC_PAD, s);
+    colsum(q, q->da1, HID, B, HID, g + L.ob1, s);
     if (!rc && hipGetLastError() != hipSuccess) rc = pfail(q, NNP_EDEVICE, "kernel launch failed");
     return rc;
 }
@@ -586,6 +658,10 @@ int nnp_proposal_create(nnp_proposal **out, const nnp_proposal_config *c, int de
     if (!rc) rc = alloc(q, &q->da1q, Bp * HID);
     if (!rc) rc = alloc(q, &q->partial, Bp);
     if (!rc) rc = alloc(q, &q->loss_tmp, 1);
+    q->splitk_floats = (size_t)32 * HID * HID;        // slices of the largest split products
+    q->splitk_floats = std::max(q->splitk_floats, (size_t)16 * L.ny_pad * HID);
+    if (!rc) rc = alloc(q, &q->splitk, q->splitk_floats);
+    if (!rc) rc = alloc(q, &q->colpart, (size_t)COL_CHUNKS * L.ny_pad);
     if (rc) {
         nnp_proposal_destroy(q);
         return pfail(nullptr, NNP_ENOMEM, "device allocation failed");
@@ -786,7 +862,7 @@ int nnp_gemm_bf16(int a_layout, int b_layout, int M, int N, int K, const uint16_
     if (lda < (a_layout ? M : K) || ldb < (b_layout ? N : K)) return NNP_EINVAL;
     if (((uintptr_t)A | (uintptr_t)B) & 15) return NNP_EINVAL;
     if (epilogue == 2 && (!mask || ldm < N)) return NNP_EINVAL;
-    GemmArgs g{A, B, lda, ldb, M, N, K, bias, mask, ldm, C, ldc, Cq, ldcq};
+    GemmArgs g{A, B, lda, ldb, M, N, K, bias, mask, ldm, C, ldc, Cq, ldcq, nullptr};
     return launch_gemm(a_layout, b_layout, epilogue, g, (hipStream_t)hip_stream);
 }
 

@@ -1,0 +1,202 @@
+"""Training and evaluation of the learned proposal (the proposal network of nnproposal.h).
+
+Labels come from the plain planner itself: for every training scene the batched planner (uniform
+Philox draws) returns its best parameter vector theta*, and the proposal network learns a Gaussian
+over theta given the scene's encoding (Gaussian NLL, Adam). Evaluation compares plans that draw
+from the proposal with plans that draw uniformly, on held-out scenes, at matched numbers of
+samples. Every computation runs in the library's HIP kernels (encoding, batched planning,
+forward/backward/Adam); this module only moves tensors between the calls.
+
+Command line (one GPU): ``python -m paper_1904_06680_amd.learn --labels 100000``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import scenes
+from .nnplan import Planner
+from .proposal import Proposal
+
+
+def init_params(n_theta: int, seed: int, enc: int = 72, hidden: int = 256) -> np.ndarray:
+    """Seeded starting parameters in the flat layout of nnproposal.h: uniform weights in
+    +-1/sqrt(fan_in) (output layer scaled by 0.1), zero hidden biases, mu biases 0 and log-sigma
+    biases log(1/sqrt(3)) (the standard deviation of the uniform draws)."""
+    rng = np.random.default_rng([int(seed), 0x9A0])
+    u = lambda shape, fan: rng.uniform(-1.0, 1.0, shape) / math.sqrt(fan)  # noqa: E731
+    parts = [u((hidden, enc), enc), np.zeros(hidden), u((hidden, hidden), hidden), np.zeros(hidden),
+             u((2 * n_theta, hidden), hidden) * 0.1,
+             np.concatenate([np.zeros(n_theta), np.full(n_theta, math.log(1.0 / math.sqrt(3.0)))])]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+class Labeller:
+    """Plain-planner labels (encoding, theta*, best cost) for C1-style scenes."""
+
+    def __init__(self, planner: Planner, proposal: Proposal, T: int = 50):
+        self.pl, self.prop, self.T = planner, proposal, T
+        self.torch = planner.torch
+
+    def plan(self, z0, goal, pts_dev, Ns, seeds, proposal=None, a_prev=None, keys=("theta", "cost")):
+        probs, keep = self.pl.array_problems(z0, goal, pts_dev, self.T, Ns, seeds, a_prev=a_prev,
+                                             proposal=proposal)
+        out = self.pl.alloc_batch(len(z0), self.T, keys)
+        self.pl.plan_batch_into(probs, out)
+        return probs, out, keep
+
+    def encode(self, probs):
+        return self.prop.encode_problems(probs)
+
+    def label(self, count: int, N: int, scene_seed: int, chunk: int = 1024, log=None):
+        torch = self.torch
+        dev = self.pl._dev()
+        z0, goal, pts = scenes.c1_arrays(scene_seed, count)
+        encs, ths, costs = [], [], []
+        for c0 in range(0, count, chunk):
+            n = min(chunk, count - c0)
+            pd = torch.from_numpy(pts[c0:c0 + n]).to(dev)
+            probs, out, keep = self.plan(z0[c0:c0 + n], goal[c0:c0 + n], pd, [N] * n,
+                                         np.arange(c0, c0 + n) + 1_000_003 * scene_seed)
+            encs.append(self.encode(probs))
+            ths.append(out["theta"])
+            costs.append(out["cost"])
+            torch.cuda.synchronize(dev)
+            del keep, pd
+            if log and (c0 // chunk) % 8 == 0:
+                log(f"labels {c0 + n}/{count}")
+        return torch.cat(encs), torch.cat(ths), torch.cat(costs)
+
+
+def train(prop: Proposal, enc, theta, epochs: int, batch: int = 1024, lr: float = 1e-3,
+          seed: int = 0, log=None) -> list:
+    """Adam on the Gaussian NLL over (enc, theta) pairs; lr drops to 0.3 lr for the last 30% of
+    the epochs. Returns the mean loss per epoch."""
+    torch = prop.torch
+    dev = prop._dev()
+    prop.set_params(torch.from_numpy(init_params(prop.n_theta, seed)).to(dev))
+    n = enc.shape[0]
+    batch = min(batch, n, prop.max_batch)
+    loss = torch.empty(1, device=dev)
+    acc = torch.zeros(1, device=dev)
+    gen = torch.Generator(device="cpu").manual_seed(int(seed))
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(dev)
+        acc.zero_()
+        steps = 0
+        rate = lr if ep < 0.7 * epochs else 0.3 * lr
+        for i in range(0, n - batch + 1, batch):
+            idx = perm[i:i + batch]
+            prop.train_step(enc[idx].contiguous(), theta[idx].contiguous(), rate, loss)
+            acc += loss
+            steps += 1
+        hist.append(float(acc.item()) / max(steps, 1))
+        if log and (ep % 5 == 0 or ep == epochs - 1):
+            log(f"epoch {ep}: loss {hist[-1]:.2f}")
+    return hist
+
+
+def _diff(a, b):
+    d = a - b
+    d[np.isinf(a) & np.isinf(b)] = 0.0
+    return d
+
+
+def evaluate(lab: Labeller, count: int, scene_seed: int, n_ref: int = 65536,
+             budgets=(1024, 2048, 4096, 8192, 16384, 32768, 65536), tau: float = 1.0,
+             fixed=(8192, 65536), log=None) -> dict:
+    """Held-out comparison on `count` scenes. b_U = best cost of n_ref uniform draws; for every
+    budget n, b_P(n) = best cost of n proposal draws (sampling width scaled by tau) and, for
+    reference, the best of n uniform draws; both as the median and the win rate of b(n) - b_U over
+    the scenes where b_U is finite. samples_to_matched_cost is the smallest budget whose median
+    difference is <= 0 (ratio = n_ref / that budget). The fixed comparison pits fixed[0] proposal
+    draws against fixed[1] uniform draws, with the uniform plan as the fallback when the
+    proposal's best is worse."""
+    torch = lab.torch
+    dev = lab.pl._dev()
+    z0, goal, pts = scenes.c1_arrays(scene_seed, count)
+    pd = torch.from_numpy(pts).to(dev)
+    seeds = np.arange(count) + 7_777_777
+    probs, out, keep = lab.plan(z0, goal, pd, [n_ref] * count, seeds)
+    enc = lab.encode(probs)
+    mu, ls = lab.prop.forward(enc)
+    ls = (ls + math.log(tau)).contiguous()
+    bU = out["cost"].cpu().numpy()
+    feas = np.isfinite(bU)
+    res = {"scenes": count, "feasible": int(feas.sum()), "n_ref": n_ref, "tau": tau,
+           "uniform": {}, "proposal": {}}
+
+    def stats(b):
+        d = _diff(b, bU)[feas]
+        return {"median_diff": float(np.median(d)), "win_rate": float(np.mean(d <= 0)),
+                "infeasible": float(np.mean(np.isinf(b[feas])))}
+
+    for n in budgets:
+        _, o, k = lab.plan(z0, goal, pd, [n] * count, seeds)
+        res["uniform"][n] = stats(o["cost"].cpu().numpy())
+        _, o, k = lab.plan(z0, goal, pd, [n] * count, seeds, proposal=(mu, ls, n))
+        res["proposal"][n] = stats(o["cost"].cpu().numpy())
+        if log:
+            log(f"N={n}: uniform {res['uniform'][n]}  proposal {res['proposal'][n]}")
+    matched = [n for n in budgets if res["proposal"][n]["median_diff"] <= 0.0]
+    res["samples_to_matched_cost"] = matched[0] if matched else None
+    res["ratio"] = n_ref / matched[0] if matched else None
+    # fixed comparison: fixed[0] proposal draws against fixed[1] uniform draws, with the uniform
+    # plan as fallback whenever the proposal's best is worse
+    n_p, n_u = fixed
+    _, o, k = lab.plan(z0, goal, pd, [n_p] * count, seeds, proposal=(mu, ls, n_p))
+    bP = o["cost"].cpu().numpy()
+    d = _diff(bP, bU)[feas]
+    res["fixed"] = {"proposal_samples": n_p, "uniform_samples": n_u,
+                    "proposal_not_worse": float(np.mean(d <= 0)),
+                    "median_diff": float(np.median(d)),
+                    "with_fallback_median_diff": float(np.median(np.minimum(d, 0.0)))}
+    del keep, k, pd
+    return res
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--labels", type=int, default=100000)
+    ap.add_argument("--label-samples", type=int, default=65536)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-scenes", type=int, default=256)
+    ap.add_argument("--tau", type=float, default=1.0)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    import torch
+    t0 = time.time()
+
+    def log(*a):
+        print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
+
+    preset = scenes.C1
+    nt = scenes.n_theta(preset["widths"])
+    pl = Planner(preset)
+    prop = Proposal(preset, nt, max(args.batch, args.eval_scenes))
+    lab = Labeller(pl, prop)
+    enc, th, cost = lab.label(args.labels, args.label_samples, scene_seed=1, log=log)
+    keep = torch.isfinite(cost)
+    enc, th = enc[keep].contiguous(), th[keep].contiguous()
+    log(f"labels: {int(keep.sum())} feasible of {args.labels}")
+    hist = train(prop, enc, th, args.epochs, args.batch, args.lr, log=log)
+    res = evaluate(lab, args.eval_scenes, scene_seed=2, tau=args.tau, log=log)
+    res.update(labels=args.labels, label_samples=args.label_samples, feasible_labels=int(keep.sum()),
+               epochs=args.epochs, final_loss=hist[-1])
+    print(json.dumps(res), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(res, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -311,6 +311,64 @@ class Planner:
                self.h)
         return res
 
+    def array_problems(self, z0, goal, pts, T: int, Ns, seeds, a_prev=None, proposal=None,
+                       warm_theta=None, insts=None):
+        """ctypes array of problems for n scenes held as arrays: z0, goal host float [n][4];
+        pts a device float32 tensor [n][P][4] (or None for no obstacles); a_prev host [n][2] or
+        None (idle); proposal = (mu, log_sigma, n_prop) with device tensors [n][n_theta] and an
+        int or per-problem counts; warm_theta a device tensor [n][n_theta] or None. The caller
+        keeps every tensor alive until the work has run. Returns (problems, host keep-alive)."""
+        n = len(z0)
+        probs = (nnp_problem * n)()
+        P = 0 if pts is None else int(pts.shape[1])
+        ap_all = None
+        if a_prev is not None:
+            ap_all = (C.c_float * (2 * n))(*np.asarray(a_prev, np.float32).ravel().tolist())
+        base = C.addressof(ap_all) if ap_all is not None else 0
+        for i in range(n):
+            pr = probs[i]
+            for k in range(4):
+                pr.z0[k] = float(z0[i][k])
+                pr.goal[k] = float(goal[i][k])
+            if ap_all is not None:
+                pr.a_prev = C.cast(base + 8 * i, C.POINTER(C.c_float))
+            pr.P = P
+            pr.obst = pts[i].data_ptr() if P else None
+            pr.N = int(Ns[i])
+            pr.T = int(T)
+            pr.seed = int(seeds[i])
+            pr.inst = 0 if insts is None else int(insts[i])
+            if warm_theta is not None:
+                pr.warm_theta = warm_theta[i].data_ptr()
+            if proposal is not None:
+                mu, ls, n_prop = proposal
+                pr.prop_mu = mu[i].data_ptr()
+                pr.prop_log_sigma = ls[i].data_ptr()
+                pr.n_prop = int(n_prop if np.isscalar(n_prop) else n_prop[i])
+        return probs, ap_all
+
+    def alloc_batch(self, n: int, T: int, keys=("theta", "cost", "best_index", "status")) -> dict:
+        """Batched output tensors (row i is problem i's result)."""
+        torch, d = self.torch, self._dev()
+        shapes = dict(theta=((n, self.n_theta), torch.float32), controls=((n, T, 2), torch.float32),
+                      controls_phys=((n, T, 2), torch.float32),
+                      traj=((n, T + 1, 4), torch.float32), cost=((n,), torch.float32),
+                      best_index=((n,), torch.int32), status=((n,), torch.int32),
+                      goal_reached=((n,), torch.int32))
+        return {k: torch.empty(*shapes[k][0], dtype=shapes[k][1], device=d) for k in keys}
+
+    def plan_batch_into(self, probs, out: dict, stream=None):
+        """nnp_plan_batch with problem i's outputs written to row i of the tensors in `out`."""
+        n = len(probs)
+        res = (nnp_result * n)()
+        for k, t in out.items():
+            stride = t.stride(0) * t.element_size()
+            base = t.data_ptr()
+            for i in range(n):
+                setattr(res[i], k, base + i * stride)
+        _check(nnp_plan_batch(self.h, probs, res, self._stream() if stream is None else stream),
+               self.h)
+
     def plan_batch(self, scenes_, Ns, seeds) -> list:
         probs, keep = self.batch_problems(scenes_, Ns, seeds)
         outs = [self.alloc_result(sc.T) for sc in scenes_]

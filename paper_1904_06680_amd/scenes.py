@@ -248,3 +248,68 @@ def batch_c2(seed: int = 0, count: int = 256, n_range=(4096, 65536), p_range=(10
         Ns.append(N)
         seeds.append(1000 * seed + i)
     return scs, Ns, seeds
+
+
+def c1_arrays(seed: int, count: int, n_static: int = 2000, n_dyn: int = 20,
+              pts_per_dyn: int = 50, box: float = 65.0):
+    """`count` scenes of the scene_c1 recipe, drawn vectorised (another stream than scene_c1, so
+    the scenes differ from scene_c1(seed)): returns z0 [count, 4], goal [count, 4] and points
+    [count, n_static + n_dyn * pts_per_dyn, 4] as float32 arrays. Used for the proposal's
+    training and held-out sets."""
+    rng = np.random.default_rng([int(seed), 0xC3])
+    z0 = np.zeros((count, 4))
+    z0[:, 2] = rng.uniform(-math.pi, math.pi, count)
+    z0[:, 3] = rng.uniform(-3.0, 15.0, count)
+    dist = rng.uniform(20.0, 60.0, count)
+    bearing = rng.uniform(-math.pi, math.pi, count)
+    goal = np.stack([dist * np.cos(bearing), dist * np.sin(bearing),
+                     rng.uniform(-math.pi, math.pi, count), np.zeros(count)], 1)
+    c, s = np.cos(z0[:, 2])[:, None], np.sin(z0[:, 2])[:, None]
+
+    def inside(x, y, dilate=0.5):
+        xi = c * x + s * y
+        eta = -s * x + c * y
+        return ((xi < C1["front"] + dilate) & (xi > -C1["rear"] - dilate)
+                & (np.abs(eta) < C1["half_width"] + dilate))
+
+    sx = rng.uniform(-box, box, (count, n_static))
+    sy = rng.uniform(-box, box, (count, n_static))
+    bad = inside(sx, sy)
+    while bad.any():
+        k = int(bad.sum())
+        sx[bad] = rng.uniform(-box, box, k)
+        sy[bad] = rng.uniform(-box, box, k)
+        bad = inside(sx, sy)
+    # moving rectangles: unit perimeter offsets, then yaw / centre per obstacle
+    per = 2.0 * (4.5 + 1.8)
+    d = (np.arange(pts_per_dyn) + 0.5) * per / pts_per_dyn
+    hl, hw = 2.25, 0.9
+    ox = np.where(d < 4.5, -hl + d, np.where(d < 6.3, hl, np.where(d < 10.8, hl - (d - 6.3), -hl)))
+    oy = np.where(d < 4.5, -hw, np.where(d < 6.3, -hw + (d - 4.5),
+                                         np.where(d < 10.8, hw, hw - (d - 10.8))))
+    cx = rng.uniform(-box, box, (count, n_dyn))
+    cy = rng.uniform(-box, box, (count, n_dyn))
+    yaw = rng.uniform(-math.pi, math.pi, (count, n_dyn))
+    vel = rng.uniform(-5.0, 5.0, (count, n_dyn, 2))
+
+    def outline():
+        cyw, syw = np.cos(yaw)[..., None], np.sin(yaw)[..., None]
+        return cx[..., None] + cyw * ox - syw * oy, cy[..., None] + syw * ox + cyw * oy
+
+    dx, dy = outline()
+    bad = inside(dx.reshape(count, -1), dy.reshape(count, -1)).reshape(count, n_dyn, -1).any(2)
+    while bad.any():
+        k = int(bad.sum())
+        cx[bad] = rng.uniform(-box, box, k)
+        cy[bad] = rng.uniform(-box, box, k)
+        yaw[bad] = rng.uniform(-math.pi, math.pi, k)
+        dx, dy = outline()
+        bad = inside(dx.reshape(count, -1), dy.reshape(count, -1)).reshape(count, n_dyn, -1).any(2)
+    P = n_static + n_dyn * pts_per_dyn
+    pts = np.zeros((count, P, 4), np.float32)
+    pts[:, :n_static, 0], pts[:, :n_static, 1] = sx, sy
+    pts[:, n_static:, 0] = dx.reshape(count, -1)
+    pts[:, n_static:, 1] = dy.reshape(count, -1)
+    pts[:, n_static:, 2] = np.repeat(vel[..., 0], pts_per_dyn, 1)
+    pts[:, n_static:, 3] = np.repeat(vel[..., 1], pts_per_dyn, 1)
+    return z0.astype(np.float32), goal.astype(np.float32), pts
