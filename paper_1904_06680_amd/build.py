@@ -1,5 +1,5 @@
-"""Build the HIP library ``libnnplan.so`` (gfx950: the planner and the proposal network) in the
-package directory with hipcc.
+"""Build the HIP library ``libnnplan.so`` (gfx950: the planner, the proposal network and the fleet
+runtime) in the package directory with hipcc.
 
 All device code is compiled without packed-FP32 instructions and without floating-point
 contraction; every fused multiply-add in the kernels is written out explicitly.
@@ -12,7 +12,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("nnplan.hip", "proposal.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("nnplan.hip", "proposal.hip", "fleet.hip")]
 LIB = os.path.join(HERE, "libnnplan.so")
 
 HIPCC_FLAGS = [

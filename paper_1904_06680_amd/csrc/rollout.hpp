@@ -249,6 +249,23 @@ struct Pose {
     }
 };
 
+// Goal tolerances of Table II at state (x, y, phi, v) with c = cos phi, s = sin phi: the goal's
+// offset in the vehicle frame within (eps_xi, eps_eta), heading error within eps_phi and speed
+// error within eps_v.
+__device__ __forceinline__ int within_tolerance(float eps_xi, float eps_eta, float eps_phi,
+                                                float eps_v, const float (&goal)[4], float x,
+                                                float y, float phi, float v, float c, float s)
+{
+    const float gx = goal[0] - x, gy = goal[1] - y;
+    const float xi_g = fmaf(c, gx, s * gy);
+    const float eta_g = fmaf(c, gy, -(s * gx));
+    float dphi = goal[2] - phi;
+    if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
+    else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+    return fabsf(xi_g) <= eps_xi && fabsf(eta_g) <= eps_eta && fabsf(dphi) <= eps_phi &&
+           fabsf(goal[3] - v) <= eps_v;
+}
+
 // ---------------------------------------------------------------------------------------------
 // One sample's closed-loop state.
 // ---------------------------------------------------------------------------------------------
@@ -372,14 +389,7 @@ struct SampleSim {
     // Tolerance test of Table II at the current state.
     __device__ __forceinline__ int goal_reached(const DevModel &m, const float (&goal)[4]) const
     {
-        const float gx = goal[0] - x, gy = goal[1] - y;
-        const float xi_g = fmaf(c, gx, s * gy);
-        const float eta_g = fmaf(c, gy, -(s * gx));
-        float dphi = goal[2] - phi;
-        if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
-        else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
-        return fabsf(xi_g) <= m.eps_xi && fabsf(eta_g) <= m.eps_eta && fabsf(dphi) <= m.eps_phi &&
-               fabsf(goal[3] - v) <= m.eps_v;
+        return within_tolerance(m.eps_xi, m.eps_eta, m.eps_phi, m.eps_v, goal, x, y, phi, v, c, s);
     }
 };
 

@@ -313,3 +313,62 @@ def c1_arrays(seed: int, count: int, n_static: int = 2000, n_dyn: int = 20,
     pts[:, n_static:, 2] = np.repeat(vel[..., 0], pts_per_dyn, 1)
     pts[:, n_static:, 3] = np.repeat(vel[..., 1], pts_per_dyn, 1)
     return z0.astype(np.float32), goal.astype(np.float32), pts
+
+
+def _rigid(rng, xy_box=20.0):
+    a = rng.uniform(-math.pi, math.pi)
+    return a, rng.uniform(-xy_box, xy_box), rng.uniform(-xy_box, xy_box)
+
+
+def _apply(a, tx, ty, z):
+    """Rigid motion (rotation a, translation tx, ty) of states [n][4] or points [n][4]
+    (x, y, heading-or-vx, v-or-vy)."""
+    c, s = math.cos(a), math.sin(a)
+    z = np.asarray(z, np.float64).reshape(-1, 4).copy()
+    x, y = z[:, 0].copy(), z[:, 1].copy()
+    z[:, 0] = c * x - s * y + tx
+    z[:, 1] = s * x + c * y + ty
+    return z
+
+
+def mission_waypoints(seed: int):
+    """Waypoint mission after Experiment 4 (Sect. III): from rest, four static setpoints with
+    position and heading that need alternating forward and reverse driving and full steering,
+    moved by a random rigid motion. Returns (z0, waypoints [4][4])."""
+    rng = np.random.default_rng([int(seed), 0xE4])
+    z0 = np.array([[0.0, 0.0, 0.0, 0.0]])
+    wps = np.array([[10.0, 5.0, math.pi / 2, 0.0],      # forward, left turn
+                    [10.0, -3.0, math.pi / 2, 0.0],     # straight back in reverse
+                    [2.0, -8.0, math.pi, 0.0],          # forward, left turn
+                    [10.0, -8.0, math.pi, 0.0]])        # straight back in reverse
+    a, tx, ty = _rigid(rng)
+    z0 = _apply(a, tx, ty, z0)
+    wps = _apply(a, tx, ty, wps)
+    z0[:, 2] = _wrap(z0[:, 2] + a)
+    wps[:, 2] = _wrap(wps[:, 2] + a)
+    return z0[0].astype(np.float32), wps.astype(np.float32)
+
+
+def parking_slot(seed: int, n_points: int = 400):
+    """Reverse parking: a 2.5 m wide, 5.5 m deep slot between two parked 1.8 x 4.5 m rectangles
+    (n_points/2 points evenly on each perimeter); the vehicle starts at rest in the aisle 6 m in
+    front of the slot, heading along the aisle, with an auxiliary waypoint past the slot and the
+    final waypoint in the slot facing out. Moved by a random rigid motion. Returns (z0,
+    waypoints [2][4], points [n_points][4] with zero velocity)."""
+    rng = np.random.default_rng([int(seed), 0x9A4])
+    half = n_points // 2
+    cars = []
+    for cx in (-(1.25 + 0.9), 1.25 + 0.9):
+        xy = rectangle_outline(cx, 0.0, math.pi / 2, 4.5, 1.8, half)
+        cars.append(np.column_stack([xy, np.zeros((half, 2))]))
+    pts = np.concatenate(cars, 0)
+    z0 = np.array([[-8.0 + rng.uniform(-1, 1), 6.0 + rng.uniform(-0.3, 0.3), 0.0, 0.0]])
+    wps = np.array([[3.5, 6.5, 0.0, 0.0],                 # auxiliary: past the slot
+                    [0.0, 0.25, math.pi / 2, 0.0]])       # in the slot, facing out
+    a, tx, ty = _rigid(rng)
+    z0 = _apply(a, tx, ty, z0)
+    wps = _apply(a, tx, ty, wps)
+    pts = _apply(a, tx, ty, pts)
+    z0[:, 2] = _wrap(z0[:, 2] + a)
+    wps[:, 2] = _wrap(wps[:, 2] + a)
+    return z0[0].astype(np.float32), wps.astype(np.float32), pts.astype(np.float32)

@@ -9,9 +9,9 @@ import subprocess
 import pytest
 
 from conftest import ROOT
-from paper_1904_06680_amd import nnplan, proposal, scenes
+from paper_1904_06680_amd import fleet, nnplan, proposal, scenes
 
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("nnplan.h", "nnproposal.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nnplan.h", "nnproposal.h", "nnfleet.h")]
 
 
 def declared_functions(header=None):
@@ -26,6 +26,7 @@ def declared_functions(header=None):
 def test_header_declares_the_binding_surface():
     assert declared_functions(HEADERS[0]) == sorted(nnplan.EXPORTED)
     assert declared_functions(HEADERS[1]) == sorted(proposal.EXPORTED)
+    assert declared_functions(HEADERS[2]) == sorted(fleet.EXPORTED)
 
 
 def test_library_exports_every_declared_symbol():
@@ -37,7 +38,7 @@ def test_library_exports_every_declared_symbol():
 
 def _c_layout(tmp_path, structs):
     """sizeof and offsetof of every field, as the C compiler lays out the header's structs."""
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nnproposal.h"',
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nnfleet.h"',
              'int main(void){']
     for name, cls in structs:
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -56,7 +57,10 @@ def _c_layout(tmp_path, structs):
 def test_struct_layouts_match_header(tmp_path):
     structs = [("nnp_model", nnplan.nnp_model), ("nnp_problem", nnplan.nnp_problem),
                ("nnp_result", nnplan.nnp_result), ("nnp_rollout_out", nnplan.nnp_rollout_out),
-               ("nnp_proposal_config", proposal.nnp_proposal_config)]
+               ("nnp_proposal_config", proposal.nnp_proposal_config),
+               ("nnp_fleet_config", fleet.nnp_fleet_config),
+               ("nnp_vehicle_spec", fleet.nnp_vehicle_spec),
+               ("nnp_vehicle_state", fleet.nnp_vehicle_state)]
     lay = _c_layout(tmp_path, structs)
     for name, cls in structs:
         assert C.sizeof(cls) == lay[name], name
