@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, learned-proposal and served legs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of planning, run a plain device copy of this many MiB "
                          "(reference kernel for scaling HBM counter readings)")
@@ -168,11 +170,93 @@ def main() -> int:
         "roofline": roof,
         "best_costs_first_scenes": [round(c, 4) for c in costs[:3]],
     }
+    if not args.no_extra:
+        line["batched_uneven"] = bench_batch(pl)
+        prop_res, prop = bench_proposal(pl)
+        line["proposal"] = prop_res
+        line["served"] = bench_served(pl, prop)
+        prop.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(scs[0], preset, args.cpu_seconds)
     pl.close()
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_batch(pl) -> dict:
+    """256 uneven problems (N, P, T spread) in one nnp_plan_batch call; lane layout from the
+    autotuner. Rollout-steps/s over the wall time of the call (mean of 3 after the tuning runs)."""
+    from paper_1904_06680_amd import autotune, scenes
+    scs, Ns, seeds = scenes.batch_c2(0)
+    tune = autotune.tune_batch(scenes.C1, scs, Ns, seeds, candidates=(4, 8, 16), reps=3)
+    steps = sum(N * sc.T for sc, N in zip(scs, Ns))
+    return {"workload": "256 problems, N log-uniform 4096-65536, P log-uniform 100-5000, "
+                        "T in {20,40,60,80}, MLP 8-32-32-2",
+            "rollout_steps": steps, "ms": round(tune["ms"], 3),
+            "value": steps / (tune["ms"] / 1e3), "unit": "rollout-steps/s",
+            "lanes_per_sample": tune["lanes_per_sample"],
+            "timings_ms": {k: round(v, 3) for k, v in tune["timings_ms"].items()}}
+
+
+def bench_proposal(pl):
+    """Reduced learned-proposal run (4096 training scenes labelled at 16384 uniform samples, 64
+    held-out scenes), plus the training step's MFMA throughput at a batch of 4096."""
+    import torch
+
+    from paper_1904_06680_amd import learn, scenes
+    from paper_1904_06680_amd.proposal import Proposal
+    nt = pl.n_theta
+    dev = pl._dev()
+    prop = Proposal(scenes.C1, nt, 4096)
+    lab = learn.Labeller(pl, prop)
+    enc, th, cost = lab.label(4096, 16384, scene_seed=1)
+    ok = torch.isfinite(cost)
+    learn.train(prop, enc[ok].contiguous(), th[ok].contiguous(), epochs=30, batch=512)
+    ev = learn.evaluate(lab, 64, scene_seed=2, budgets=(1024, 4096, 16384, 65536))
+    # training-step throughput (forward + NLL + backward + Adam) at B = 4096
+    B = 4096
+    X = torch.randn(B, 72, device=dev)
+    T = torch.rand(B, nt, device=dev) * 2 - 1
+    loss = torch.empty(1, device=dev)
+    snap = prop.get_params()
+    for _ in range(3):
+        prop.train_step(X, T, 1e-6, loss)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        prop.train_step(X, T, 1e-6, loss)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / 20
+    prop.set_params(snap)
+    lin = 72 * 256 + 256 * 256 + 256 * 2 * nt
+    flops = 2.0 * B * (2 * lin + (256 * 256 + 256 * 2 * nt))
+    res = {"workload": "reduced: 4096 labelled C1-style scenes (16384 uniform samples each), "
+                       "64 held-out scenes; uniform reference 65536 samples",
+           "feasible_labels": int(ok.sum()), "samples_to_matched_cost": ev["samples_to_matched_cost"],
+           "ratio": ev["ratio"], "fixed_8192_vs_65536": ev["fixed"],
+           "median_diff_by_budget": {n: round(ev["proposal"][n]["median_diff"], 4)
+                                     for n in ev["proposal"]},
+           "uniform_median_diff_by_budget": {n: round(ev["uniform"][n]["median_diff"], 4)
+                                             for n in ev["uniform"]},
+           "train_roofline": {"bound": "mfma", "batch": B, "ms": round(ms, 4),
+                              "achieved": round(flops / ms / 1e9, 3), "peak": 2500.0,
+                              "unit": "TFLOP/s", "frac": round(flops / ms / 1e9 / 2500.0, 5),
+                              "dtype": "bf16 products, f32 accumulate"}}
+    return res, prop
+
+
+def bench_served(pl, prop) -> dict:
+    """Closed loop served: 64 vehicles (waypoint missions and reverse parking) x 200 steps, each
+    plan 8192 proposal + 8192 uniform samples over T = 50."""
+    from paper_1904_06680_amd import serve
+    vs, kinds = serve.c4_vehicles(64, device=pl._dev())
+    r = serve.run(pl, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
+    return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50",
+            "latency_ms_p50": round(r["latency_ms"]["p50"], 3),
+            "latency_ms_p99": round(r["latency_ms"]["p99"], 3),
+            "rollout_steps_per_s": r["rollout_steps_per_s"],
+            "missions_completed": r["missions_completed"]}
 
 
 if __name__ == "__main__":

@@ -11,7 +11,8 @@
  * is the plan's first predicted state), the mission check (Step 7), and the obstacles' constant-
  * velocity motion to t+1. Samples per plan: n_prop draws from the learned proposal (encoding and
  * network of include/nnproposal.h, evaluated on the GPU every step) plus n_uniform uniform draws;
- * the Philox instance word is the step index, so every step draws fresh samples.
+ * the Philox key of vehicle i is seed + i and the instance word is the step index, so vehicles
+ * and steps draw independent samples.
  *
  * Conventions are those of include/nnplan.h.
  */
@@ -32,7 +33,7 @@ typedef struct nnp_fleet_config {
     int32_t T;                 /* horizon of every plan                                       */
     int32_t n_uniform;         /* uniform samples per plan (>= 1)                             */
     int32_t n_prop;            /* proposal samples per plan (0 = plain sampler)                */
-    uint64_t seed;             /* Philox key of every plan                                    */
+    uint64_t seed;             /* Philox key of vehicle i's plans: seed + i                    */
     int32_t warm_start;        /* 1: theta*_{t-1} replaces sample 0 from the second step on    */
     float dt;                  /* sampling time T_s (obstacle motion between steps)           */
     float eps_xi, eps_eta, eps_phi, eps_v; /* waypoint tolerances (Table II)                  */

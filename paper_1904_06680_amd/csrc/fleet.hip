@@ -242,7 +242,7 @@ int nnp_fleet_step(nnp_fleet *f, void *hip_stream, double *latency_ms, int32_t *
         p.N = c.n_prop + c.n_uniform;
         p.T = c.T;
         p.inst = (uint32_t)f->tick;
-        p.seed = c.seed;
+        p.seed = c.seed + (uint64_t)i;      // one Philox key per vehicle
         p.warm_theta = (c.warm_start && v.steps > 0) ? warm_in + (size_t)i * nt : nullptr;
         if (f->prop) {
             p.n_prop = c.n_prop;

@@ -61,10 +61,11 @@ def lib():
 
 class Fleet:
     """Vehicles: list of dicts with z0 [4], waypoints [[x, y, phi, v], ...] and points (a device
-    float32 tensor [P][4] or None)."""
+    float32 tensor [P][4] or None). Waypoint tolerances default to the planner preset's (Table
+    II); `tolerances` overrides any of eps_xi, eps_eta, eps_phi, eps_v."""
 
     def __init__(self, planner, vehicles, T: int, n_uniform: int, n_prop: int = 0,
-                 proposal=None, seed: int = 0, warm_start: bool = True):
+                 proposal=None, seed: int = 0, warm_start: bool = True, tolerances=None):
         import torch
         self.torch = torch
         self.planner = planner
@@ -73,7 +74,8 @@ class Fleet:
         c = nnp_fleet_config()
         c.n_vehicles, c.T, c.n_uniform, c.n_prop = len(vehicles), T, n_uniform, n_prop
         c.seed, c.warm_start, c.dt = seed, int(warm_start), float(p["dt"])
-        c.eps_xi, c.eps_eta, c.eps_phi, c.eps_v = (float(p[k]) for k in
+        tol = dict(p, **(tolerances or {}))
+        c.eps_xi, c.eps_eta, c.eps_phi, c.eps_v = (float(tol[k]) for k in
                                                    ("eps_xi", "eps_eta", "eps_phi", "eps_v"))
         specs = (nnp_vehicle_spec * len(vehicles))()
         self._keep = []

@@ -1,7 +1,7 @@
 """GPU tests of the served closed loop (include/nnfleet.h): every fleet step must equal an
 independent nnp_plan call on the same inputs (current state, current waypoint, previous controls,
-warm start with the previous best parameters, Philox instance = step index, obstacles moved by
-their velocities), bit for bit; waypoint switching and mission completion follow the tolerances.
+warm start with the previous best parameters, Philox key = seed + vehicle index and instance =
+step index, obstacles moved by their velocities), bit for bit; waypoint switching and mission completion follow the tolerances.
 """
 import numpy as np
 import pytest
@@ -44,7 +44,7 @@ def replicate(pl, vehicles, steps, T, N, seed, proposal=None, n_prop=0):
     """Per-vehicle nnp_plan calls that mirror the fleet (no waypoint is reached in these runs)."""
     dt = np.float32(scenes.C1["dt"])
     out = []
-    for v in vehicles:
+    for iv, v in enumerate(vehicles):
         z = np.asarray(v["z0"], np.float32)
         a_prev = None
         warm = None
@@ -55,12 +55,12 @@ def replicate(pl, vehicles, steps, T, N, seed, proposal=None, n_prop=0):
                               else pts, T, a_prev=a_prev)
             prop = None
             if proposal is not None:
-                pr, keep = pl.problem(sc, N, seed, inst=t)
+                pr, keep = pl.problem(sc, N, seed + iv, inst=t)
                 arr = (nnp_problem * 1)(pr)
                 enc = proposal.encode_problems(arr)
                 mu, ls = proposal.forward(enc)
                 prop = (mu[0].contiguous(), ls[0].contiguous(), n_prop)
-            res = pl.plan(sc, N, seed=seed, inst=t, warm_theta=warm, proposal=prop)
+            res = pl.plan(sc, N, seed=seed + iv, inst=t, warm_theta=warm, proposal=prop)
             z = res["traj"][1].cpu().numpy()
             a_prev = res["controls"][0].cpu().numpy()
             warm = res["theta"].clone()
