@@ -74,6 +74,9 @@ def load_library(path: str = LIB):
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built: run `python -m paper_1904_06680_amd.build` "
                           "(or __graft_entry__.build())")
+    # torch brings its own HIP runtime; it has to be in the process first so that the library
+    # binds to that same runtime (two runtimes in one process do not share the device).
+    import torch  # noqa: F401
     L = C.CDLL(path)
     H = C.c_void_p
     sig = {
