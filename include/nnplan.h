@@ -144,8 +144,8 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
 
 /* Many independent problems in one call: the same plan as nnp_plan for every probs[i] (each with
  * its own N, T, P, obstacles, seed and warm start), written to results[i]. All problems are
- * rolled out by one persistent launch that drains a work queue of (problem, block of samples)
- * items, longest problems first, so uneven sizes share the GPU without a launch per problem.
+ * rolled out by one launch of one workgroup per (problem, block of samples) item, longest
+ * problems first, so uneven sizes share the GPU without a launch per problem.
  * The call copies `count` problem descriptors to the device through a pinned staging buffer
  * owned by the handle (it waits for the previous batch's copy before reusing it) and enqueues
  * three kernels. Results are bit-identical to nnp_plan on each problem and to every lane layout.

@@ -86,15 +86,11 @@ __global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__rest
 }
 
 // The same table for every problem of a batch: blockIdx.y is the problem, the x blocks stride
-// over its entries. Also resets the problems' argmin keys and the work-queue counter.
-__global__ __launch_bounds__(BLOCK) void extrapolate_batch_kernel(const RolloutArgs *probs,
-                                                                  unsigned *counter)
+// over its entries. Also resets the problems' argmin keys.
+__global__ __launch_bounds__(BLOCK) void extrapolate_batch_kernel(const RolloutArgs *probs)
 {
     const RolloutArgs &a = probs[blockIdx.y];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *a.best_key = ~0ull;
-        if (blockIdx.y == 0) *counter = 0u;
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.best_key = ~0ull;
     if (a.P == 0) return;
     const long long n = (long long)(a.T + 1) * a.P2;
     float4 *ext = const_cast<float4 *>(a.ext);
@@ -368,26 +364,18 @@ __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_kerne
     rollout_tile<NetT, K, MODE>(a, blockIdx.x, sh);
 }
 
-// NEXT: many problems of uneven size in one persistent launch. Work items (problem, tile) are
-// taken from a global counter in the order the host wrote them (longest first); every
-// workgroup loops until the list is exhausted, so every wave reaches the exit.
+// Many problems of uneven size in one launch: one workgroup per work item (problem, tile of S
+// samples). The host writes the items longest problems first and the dispatcher starts
+// workgroups in grid order, so short problems fill the tail. The item index comes from
+// blockIdx, so the problem descriptor is read with scalar loads, like a kernel argument.
 template <class NetT, int K>
 __global__ __launch_bounds__(rollout_block(K))
 __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_batch_kernel(
-    const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items, int n_items,
-    unsigned *counter)
+    const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items)
 {
     __shared__ RolloutShared<K> sh;
-    __shared__ int cur;
-    for (;;) {
-        __syncthreads();                       // the previous item is done with the LDS
-        if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int w = cur;
-        if (w >= n_items) break;
-        const int2 item = items[w];
-        rollout_tile<NetT, K, MODE_PLAN>(probs[item.x], item.y, sh);
-    }
+    const int2 item = items[blockIdx.x];
+    rollout_tile<NetT, K, MODE_PLAN>(probs[item.x], item.y, sh);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -504,10 +492,8 @@ struct Variant {
     int n_layers, feature_set, K, ntheta;
     void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
-    void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int, unsigned *, int grid,
-                                 hipStream_t);
+    void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, hipStream_t);
     void (*launch_replay_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
-    int (*batch_blocks_per_cu)();
 };
 
 template <class NetT, int K>
@@ -529,10 +515,10 @@ void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
 
 template <class NetT, int K>
 void launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items,
-                            unsigned *counter, int grid, hipStream_t s)
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL((rollout_batch_kernel<NetT, K>), dim3(grid), dim3(rollout_block(K)), 0, s,
-                       probs, items, n_items, counter);
+    hipLaunchKernelGGL((rollout_batch_kernel<NetT, K>), dim3(n_items), dim3(rollout_block(K)), 0,
+                       s, probs, items);
 }
 
 template <class NetT, int K>
@@ -543,23 +529,12 @@ void launch_replay_batch_t(const RolloutArgs *probs, const ReplayOut *outs, int 
                        outs);
 }
 
-template <class NetT, int K>
-int batch_blocks_per_cu_t()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rollout_batch_kernel<NetT, K>,
-                                                     rollout_block(K), 0) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
-}
-
 #define NNP_VARIANT(NIN, H1, H2, FEAT, K)                                                         \
     {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, K,                              \
      Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, K>,                  \
      launch_replay_t<Net<NIN, H1, H2, FEAT>, K>,                                                   \
      launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                            \
-     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                             \
-     batch_blocks_per_cu_t<Net<NIN, H1, H2, FEAT>, K>}
+     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>}
 
 const Variant kVariants[] = {
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
@@ -599,12 +574,10 @@ struct nnp_handle {
     unsigned long long *d_key = nullptr;
     float4 *d_ext = nullptr;
     size_t ext_bytes = 0;
-    // batched planning: tables, keys, work-queue counter, descriptors (device and pinned host)
+    // batched planning: tables, keys, descriptors (device and pinned host)
     void *d_bext = nullptr, *d_bkeys = nullptr, *d_bmeta = nullptr, *h_bmeta = nullptr;
     size_t bext_bytes = 0, bkeys_bytes = 0, bmeta_bytes = 0, hmeta_bytes = 0;
-    unsigned *d_counter = nullptr;
     hipEvent_t meta_copied = nullptr;
-    int num_cus = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
@@ -888,7 +861,6 @@ void nnp_destroy(nnp_handle *h)
     if (h->d_bext) hipFree(h->d_bext);
     if (h->d_bkeys) hipFree(h->d_bkeys);
     if (h->d_bmeta) hipFree(h->d_bmeta);
-    if (h->d_counter) hipFree(h->d_counter);
     if (h->h_bmeta) hipHostFree(h->h_bmeta);
     if (h->meta_copied) hipEventDestroy(h->meta_copied);
     delete h;
@@ -950,7 +922,7 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
                         (size_t)n_items * sizeof(int2);
     if (capturing && (entries * sizeof(float4) > h->bext_bytes || (size_t)count * 8 >
                       h->bkeys_bytes || meta > h->bmeta_bytes || meta > h->hmeta_bytes ||
-                      !h->d_counter || !h->meta_copied || !h->num_cus))
+                      !h->meta_copied))
         return fail(h, NNP_EINVAL, "the batch workspace must be sized by an uncaptured call "
                                    "with at least this batch before capture");
     // Device workspace.
@@ -958,8 +930,6 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
     if (!rc) rc = grow(h, &h->d_bkeys, &h->bkeys_bytes, (size_t)count * 8, s, "batch keys");
     if (!rc) rc = grow(h, &h->d_bmeta, &h->bmeta_bytes, meta, s, "batch descriptors");
     if (rc) return rc;
-    if (!h->d_counter && hipMalloc(&h->d_counter, sizeof(unsigned)) != hipSuccess)
-        return fail(h, NNP_ENOMEM, "hipMalloc of the work counter failed");
     if (!h->meta_copied && hipEventCreateWithFlags(&h->meta_copied, hipEventDisableTiming) !=
                                hipSuccess)
         return fail(h, NNP_EDEVICE, "hipEventCreate failed");
@@ -1004,17 +974,10 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
         e = hipEventRecord(h->meta_copied, s);
         if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     }
-    hipLaunchKernelGGL(extrapolate_batch_kernel, dim3(64, count), dim3(BLOCK), 0, s, d_args,
-                       h->d_counter);
+    hipLaunchKernelGGL(extrapolate_batch_kernel, dim3(64, count), dim3(BLOCK), 0, s, d_args);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "extrapolate_batch_kernel launch");
-    if (!h->num_cus) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) return fail(h, NNP_EDEVICE, "props");
-        h->num_cus = prop.multiProcessorCount;
-    }
-    const int grid = std::min(n_items, h->num_cus * h->var->batch_blocks_per_cu());
-    h->var->launch_rollout_batch(d_args, d_items, n_items, h->d_counter, grid, s);
+    h->var->launch_rollout_batch(d_args, d_items, n_items, s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "rollout_batch_kernel launch");
     h->var->launch_replay_batch(d_args, d_outs, count, s);
