@@ -182,15 +182,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g)
         }
 }
 
-// Split-K finish: C[m][n] = sum over slices z = 0..S-1, in slice order (deterministic).
-__global__ void splitk_reduce_kernel(const float *__restrict__ partial, int S, int M, int N,
-                                     float *__restrict__ C, int ldc)
+// Split-K finish: acc = sum over slices z = 0..S-1 in slice order (deterministic), then the
+// same epilogue as gemm_kernel.
+template <int EPI>
+__global__ void splitk_reduce_kernel(const float *__restrict__ partial, int S, const GemmArgs g)
 {
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (size_t)M * N) return;
+    if (i >= (size_t)g.M * g.N) return;
+    const int row = (int)(i / g.N), col = (int)(i % g.N);
     float acc = 0.0f;
-    for (int z = 0; z < S; ++z) acc += partial[(size_t)z * M * N + i];
-    C[(i / N) * ldc + i % N] = acc;
+    for (int z = 0; z < S; ++z) acc += partial[(size_t)z * g.M * g.N + i];
+    float v = acc + ((EPI != 2 && g.bias) ? g.bias[col] : 0.0f);
+    if (EPI == 2) v = g.mask[(size_t)row * g.ldm + col] > 0.0f ? acc : 0.0f;
+    if (g.C) g.C[(size_t)row * g.ldc + col] = v;
+    if (g.Cq) g.Cq[(size_t)row * g.ldcq + col] = to_bf16(EPI == 1 ? fmaxf(v, 0.0f) : v);
 }
 
 int launch_gemm(int la, int lb, int epi, const GemmArgs &g, hipStream_t s, int splits = 1)
@@ -354,12 +359,21 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ y, 
     if (tid == 0) partial[b] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void loss_final_kernel(const float *__restrict__ partial, int B, float *__restrict__ loss)
+// Mean of the per-row partial losses: 256 strided binary64 sums, then a fixed-order tree.
+__global__ __launch_bounds__(256) void loss_final_kernel(const float *__restrict__ partial, int B,
+                                                         float *__restrict__ loss)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < B; ++b) s += partial[b];
-    *loss = (float)(s / B);
+    for (int b = tid; b < B; b += 256) s += partial[b];
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) *loss = (float)(red[0] / B);
 }
 
 // Column sums over rows b < B: chunk c = blockIdx.y of gridDim.y sums its rows in row order into
@@ -493,32 +507,40 @@ int alloc(nnp_proposal *q, T **p, size_t count)
     return NNP_OK;
 }
 
+// A product of the network. Shapes with fewer than 256 output tiles and a long K (the batch, or
+// the 2 n_theta outputs) split K over enough slices to give the GPU about 512 workgroups; the
+// slices are reduced in order and the epilogue runs on the sum.
 int gemm(nnp_proposal *q, int la, int lb, int epi, int M, int N, int K, const uint16_t *A, int lda,
          const uint16_t *B, int ldb, const float *bias, const float *mask, int ldm, float *C,
          int ldc, uint16_t *Cq, int ldcq, hipStream_t s)
 {
     GemmArgs g{A, B, lda, ldb, M, N, K, bias, mask, ldm, C, ldc, Cq, ldcq, nullptr};
-    const int rc = launch_gemm(la, lb, epi, g, s);
+    const int tiles = (M / TM) * (N / TN), nkt = K / TK;
+    int S = 1;
+    if (tiles < 256 && nkt >= 16) {
+        S = std::min(std::min((512 + tiles - 1) / tiles, nkt / 4), 32);
+        while (S > 1 && (size_t)S * M * N > q->splitk_floats) --S;
+    }
+    if (S <= 1) {
+        const int rc = launch_gemm(la, lb, epi, g, s);
+        if (rc) return pfail(q, rc, "GEMM launch failed");
+        return NNP_OK;
+    }
+    GemmArgs gs = g;
+    gs.partial = q->splitk;
+    int rc = launch_gemm(la, lb, 0, gs, s, S);
     if (rc) return pfail(q, rc, "GEMM launch failed");
+    const dim3 grid(blocks((size_t)M * N)), block(256);
+    if (epi == 0) hipLaunchKernelGGL(splitk_reduce_kernel<0>, grid, block, 0, s, q->splitk, S, g);
+    else if (epi == 1) hipLaunchKernelGGL(splitk_reduce_kernel<1>, grid, block, 0, s, q->splitk, S, g);
+    else hipLaunchKernelGGL(splitk_reduce_kernel<2>, grid, block, 0, s, q->splitk, S, g);
     return NNP_OK;
 }
 
-// Weight gradient C = A^T-style product with a long K (the batch): split K over enough slices to
-// give the GPU about 512 workgroups, then reduce the slices in order.
 int gemm_splitk(nnp_proposal *q, int la, int lb, int M, int N, int K, const uint16_t *A, int lda,
                 const uint16_t *B, int ldb, float *C, int ldc, hipStream_t s)
 {
-    const int tiles = (M / TM) * (N / TN), nkt = K / TK;
-    int S = std::min(std::min((512 + tiles - 1) / tiles, nkt), 32);
-    while (S > 1 && (size_t)S * M * N > q->splitk_floats) --S;
-    if (S <= 1) return gemm(q, la, lb, 0, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, ldc,
-                            nullptr, 0, s);
-    GemmArgs g{A, B, lda, ldb, M, N, K, nullptr, nullptr, 0, nullptr, 0, nullptr, 0, q->splitk};
-    int rc = launch_gemm(la, lb, 0, g, s, S);
-    if (rc) return pfail(q, rc, "GEMM launch failed");
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks((size_t)M * N)), dim3(256), 0, s,
-                       q->splitk, S, M, N, C, ldc);
-    return NNP_OK;
+    return gemm(q, la, lb, 0, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, ldc, nullptr, 0, s);
 }
 
 // Column sums over the first B rows in two deterministic passes: COL_CHUNKS row chunks, then the
@@ -554,7 +576,7 @@ int backward_ws(nnp_proposal *q, const float *ts, int B, int Bp, float *loss, hi
     hipLaunchKernelGGL(loss_kernel, dim3(Bp), dim3(256), 0, s, q->y, L.ny_pad, ts, nt, B, q->dyf,
                        q->dyq, q->partial);
     if (loss)
-        hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, q->partial, B, loss);
+        hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, q->partial, B, loss);
     float *g = q->grads;
     // layer 3: dW3 = dy^T h2q, db3 = colsum(dy), dh2 = dy W3 -> da2 = dh2 * [a2 > 0]
     int rc = gemm_splitk(q, 1, 1, L.ny_pad, HID, Bp, q->dyq, L.ny_pad, q->h2q, HID, g + L.oW3,
