@@ -72,6 +72,8 @@ typedef struct nnp_model {
     float effort_weight;             /* cost = |p_T - g_xy| + effort_weight*T_s*sum|a_h|^2     */
     float eps_xi, eps_eta, eps_phi, eps_v; /* goal tolerances for the goal_reached flag          */
     int32_t lanes_per_sample;        /* 0 = library default for the network; 1, 2, 4, 8, 16    */
+    float goal_heading_weight;       /* optional terminal terms of the cost (>= 0; 0 = off):   */
+    float goal_speed_weight;         /* + w_phi |wrap(phi_g - phi_T)| + w_v |v_g - v_T|        */
 } nnp_model;
 
 /* One planning problem at sampling time t (Sect. II-E, fourth comment: what is passed to the GPU

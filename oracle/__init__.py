@@ -40,7 +40,8 @@ class Model(C.Structure):
         ("norm_xi", C.c_double), ("norm_eta", C.c_double), ("norm_phi", C.c_double),
         ("norm_v", C.c_double), ("d_cap", C.c_double), ("effort_weight", C.c_double),
         ("eps_xi", C.c_double), ("eps_eta", C.c_double), ("eps_phi", C.c_double),
-        ("eps_v", C.c_double),
+        ("eps_v", C.c_double), ("goal_heading_weight", C.c_double),
+        ("goal_speed_weight", C.c_double),
     ]
 
 
@@ -130,6 +131,8 @@ def make_model(p: dict) -> Model:
     for i in range(MAX_LAYERS + 1):
         m.widths[i] = widths[i] if i < len(widths) else 0
     m.feature_set = int(p["feature_set"])
+    m.goal_heading_weight = float(np.float32(p.get("goal_heading_weight", 0.0)))
+    m.goal_speed_weight = float(np.float32(p.get("goal_speed_weight", 0.0)))
     return m
 
 

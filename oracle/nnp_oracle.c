@@ -277,7 +277,8 @@ static int goal_reached(const orc_model *m, const double z[4], const double goal
 /* One sample: the parameters are held constant over the horizon (Sect. IV, first comment), the */
 /* closed loop runs for h = 0..H, collision is checked at every h including h = 0 (eq. (2)), and */
 /* the cost is the terminal distance to the goal position plus effort_weight * T_s * sum |a|^2, */
-/* +inf on any collision.                                                                        */
+/* +inf on any collision. Two optional terms (weights 0 by default) add the terminal heading and */
+/* speed errors to the goal setpoint, for missions whose setpoints prescribe them (Sect. III).   */
 /* fp32_state = 1 rounds the state to float after every step; 2 also rounds the features and the */
 /* applied controls. The tests use the gap to the plain run to recognise samples whose outcome is */
 /* ill-conditioned at float precision.                                                           */
@@ -345,6 +346,8 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
     }
     double gx = z[0] - sc->goal[0], gy = z[1] - sc->goal[1];
     double cost = sqrt(gx * gx + gy * gy) + m->effort_weight * m->dt * effort;
+    cost += m->goal_heading_weight * fabs(orc_wrap_angle(sc->goal[2] - z[2]));
+    cost += m->goal_speed_weight * fabs(sc->goal[3] - z[3]);
     if (collided || isnan(cost)) cost = INFINITY;
     rec->cost = cost;
     rec->collided = collided;

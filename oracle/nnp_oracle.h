@@ -42,6 +42,8 @@ typedef struct {
     double d_cap;                 /* cap of the nearest-obstacle distance feature              */
     double effort_weight;         /* weight of the control-effort term of the cost             */
     double eps_xi, eps_eta, eps_phi, eps_v; /* goal tolerances (Table II)                       */
+    double goal_heading_weight;   /* optional terminal cost terms (0 = off): weight of          */
+    double goal_speed_weight;     /* |wrap(phi_g - phi_T)| and of |v_g - v_T|                   */
 } orc_model;
 
 typedef struct {

@@ -611,13 +611,15 @@ int check_model(const nnp_model *m, std::string &why)
             return NNP_EINVAL;
         }
     const float fin[] = {m->lf, m->lr, m->front, m->rear, m->delta_rate_max, m->u_min, m->u_max,
-                         m->effort_weight, m->eps_xi, m->eps_eta, m->eps_phi, m->eps_v};
+                         m->effort_weight, m->eps_xi, m->eps_eta, m->eps_phi, m->eps_v,
+                         m->goal_heading_weight, m->goal_speed_weight};
     for (float f : fin)
         if (!finite_f(f)) {
             why = "model constants must be finite";
             return NNP_EINVAL;
         }
     if (m->lr < 0.0f || m->front + m->rear <= 0.0f || m->delta_rate_max < 0.0f ||
+        m->goal_heading_weight < 0.0f || m->goal_speed_weight < 0.0f ||
         !(m->u_max >= m->u_min) || isnan(m->v_min) || isnan(m->v_max) || !(m->v_max >= m->v_min)) {
         why = "inconsistent model bounds (lr >= 0, rate >= 0, u_min <= u_max, v_min <= v_max)";
         return NNP_EINVAL;
@@ -668,6 +670,8 @@ DevModel derive(const nnp_model *m)
     d.d_cap = m->d_cap;
     d.inv_dcap = 1.0f / m->d_cap;
     d.effort_scale = m->effort_weight * m->dt;
+    d.w_phi = m->goal_heading_weight;
+    d.w_v = m->goal_speed_weight;
     d.eps_xi = m->eps_xi;
     d.eps_eta = m->eps_eta;
     d.eps_phi = m->eps_phi;

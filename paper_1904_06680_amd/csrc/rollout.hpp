@@ -35,6 +35,7 @@ struct DevModel {
     float inv_nxi, inv_neta, inv_nphi, inv_nv;
     float d_cap, inv_dcap;
     float effort_scale;                // effort_weight * dt
+    float w_phi, w_v;                  // terminal heading / speed weights (0 = off)
     float eps_xi, eps_eta, eps_phi, eps_v;
 };
 
@@ -382,6 +383,13 @@ struct SampleSim {
     {
         const float gx = x - goal[0], gy = y - goal[1];
         float J = sqrtf(fmaf(gx, gx, gy * gy)) + m.effort_scale * effort;
+        if (m.w_phi > 0.0f) {
+            float dphi = goal[2] - phi;
+            if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
+            else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+            J += m.w_phi * fabsf(dphi);
+        }
+        if (m.w_v > 0.0f) J += m.w_v * fabsf(goal[3] - v);
         if (first >= 0 || J != J) J = INFINITY;
         return J;
     }

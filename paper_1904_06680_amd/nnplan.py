@@ -36,6 +36,7 @@ class nnp_model(C.Structure):
         ("norm_v", C.c_float), ("d_cap", C.c_float), ("effort_weight", C.c_float),
         ("eps_xi", C.c_float), ("eps_eta", C.c_float), ("eps_phi", C.c_float),
         ("eps_v", C.c_float), ("lanes_per_sample", C.c_int32),
+        ("goal_heading_weight", C.c_float), ("goal_speed_weight", C.c_float),
     ]
 
 
@@ -181,6 +182,8 @@ def make_model(p: dict, lanes_per_sample: int = 0) -> nnp_model:
         m.widths[i] = widths[i] if i < len(widths) else 0
     m.feature_set = int(p["feature_set"])
     m.lanes_per_sample = int(lanes_per_sample)
+    m.goal_heading_weight = float(np.float32(p.get("goal_heading_weight", 0.0)))
+    m.goal_speed_weight = float(np.float32(p.get("goal_speed_weight", 0.0)))
     return m
 
 

@@ -8,7 +8,8 @@ three waypoints "1", the auxiliary [0, 0, pi/2, 0] and "2", or only the auxiliar
 The run reports, per the paper's quantities, missions solved, the computation time per sampling
 time (here: one batched plan for all seeds, and its share per vehicle), the speed range in km/h
 and the driven path length. The paper's numbers come from TSHC on a Titan V and are context, not a
-parity target (its seeds and samples are unpublished).
+parity target (its seeds and samples are unpublished). ``--goal-terms`` adds the optional
+terminal heading and speed terms to the cost (the setpoints prescribe heading and speed).
 
 Command line (one GPU): ``python -m paper_1904_06680_amd.paper_runs``.
 """
@@ -40,6 +41,8 @@ PAPER_EXP5 = {3: dict(tau_a_s=0.088, v_kmh=(-17.3, -1.2, 16.2), path_m=(13.8, 14
 
 def exp5(planner: Planner, n_waypoints: int, seeds: int = 10, N: int = 65536, H: int = 200,
          max_steps: int = 600, seed: int = 0) -> dict:
+    """One Experiment 5 mission for `seeds` vehicles (one per seed) until all are done or
+    max_steps sampling times have passed."""
     import torch
     pts = np.zeros((len(EXP5_POINTS), 4), np.float32)
     pts[:, :2] = EXP5_POINTS
@@ -72,6 +75,8 @@ def exp5(planner: Planner, n_waypoints: int, seeds: int = 10, N: int = 65536, H:
         "v_kmh_min_mean_max": [float(v_all.min()), float(v_all.mean()), float(v_all.max())],
         "path_m_min_mean_max": [min(paths), float(np.mean(paths)), max(paths)],
         "infeasible_plans": int(sum(s["infeasible_steps"] for s in st)),
+        "goal_heading_weight": float(planner.preset.get("goal_heading_weight", 0.0)),
+        "goal_speed_weight": float(planner.preset.get("goal_speed_weight", 0.0)),
         "paper": PAPER_EXP5[n_waypoints],
     }
 
@@ -81,9 +86,14 @@ def main(argv=None) -> int:
     ap.add_argument("--samples", type=int, default=65536)
     ap.add_argument("--seeds", type=int, default=10)
     ap.add_argument("--max-steps", type=int, default=600)
+    ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
+                    help="add the optional terminal heading / speed terms to the cost")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    pl = Planner(scenes.PAPER)
+    preset = dict(scenes.PAPER)
+    if args.goal_terms:
+        preset.update(goal_heading_weight=args.goal_terms[0], goal_speed_weight=args.goal_terms[1])
+    pl = Planner(preset)
     res = [exp5(pl, w, args.seeds, args.samples, max_steps=args.max_steps) for w in (3, 2)]
     for r in res:
         print(json.dumps(r), flush=True)

@@ -88,6 +88,8 @@ def main(argv=None) -> int:
     ap.add_argument("--label-samples", type=int, default=16384)
     ap.add_argument("--position-only", action="store_true",
                     help="switch waypoints on position (eps_xi, eps_eta) alone")
+    ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
+                    help="add the optional terminal heading / speed terms to the cost")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     import torch
@@ -96,7 +98,9 @@ def main(argv=None) -> int:
     def log(*a):
         print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
 
-    preset = scenes.C1
+    preset = dict(scenes.C1)
+    if args.goal_terms:
+        preset.update(goal_heading_weight=args.goal_terms[0], goal_speed_weight=args.goal_terms[1])
     nt = scenes.n_theta(preset["widths"])
     pl = Planner(preset)
     prop = None
@@ -111,6 +115,7 @@ def main(argv=None) -> int:
     res = run(pl, vs, kinds, args.steps, args.T, args.uniform, args.prop, proposal=prop,
               tolerances=tol, log=log)
     res["tolerances"] = "position only" if args.position_only else "Table II"
+    res["goal_terms"] = args.goal_terms
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

@@ -266,3 +266,26 @@ def test_paper_preset_parity(widths):
     assert np.all(np.abs(np.diff(a0, axis=1)) <= 0.05 + 1e-6)
     assert np.all(np.abs(a0[:, 0]) <= 0.05 + 1e-6)
     pl.close()
+
+
+@pytest.mark.parametrize("preset_name", ["c0", "paper"])
+def test_goal_heading_and_speed_cost_terms_parity(preset_name):
+    """The optional terminal heading and speed terms of the cost, on the GPU against the oracle,
+    and the plan's argmin under them."""
+    base = scenes.C0 if preset_name == "c0" else scenes.PAPER
+    preset = dict(base, goal_heading_weight=3.0, goal_speed_weight=0.5)
+    sc = scenes.scene_c0(6) if preset_name == "c0" else scenes.scene_exp5_parking(T=60)
+    N = 768
+    say(f"goal-state cost terms ({preset_name}): N={N}, T={sc.T}")
+    pl = Planner(preset)
+    g = np_out(pl.rollout(sc, N, seed=21))
+    st = check_samples(preset, sc, g, np.arange(N), 21)
+    say("  ", st)
+    assert st["ill_conditioned"] <= (0.05 if preset_name == "c0" else 0.5) * N, st
+    out = pl.plan(sc, N, seed=21)
+    gc = g["cost"]
+    assert int(out["best_index"].item()) == int(np.flatnonzero(gc == gc.min())[0])
+    m, ob = oracle_scene(preset, sc)
+    ref = oracle.plan(m, ob, N, seed=21)
+    say("  argmin:", check_argmin(ref["cost"], int(out["best_index"].item())))
+    pl.close()

@@ -423,6 +423,24 @@ def test_rollout_constant_control_closed_form_and_cost():
     assert np.allclose(r["traj"], zs, atol=1e-12)
 
 
+def test_optional_goal_heading_and_speed_cost_terms():
+    """Constant straight driving ends at heading 0.3 and speed 2 (constant-speed closed form);
+    with goal heading -3.0 the wrapped error is 2*pi - 3.3, and with goal speed 0.5 the speed
+    error is 1.5, each added with its weight; zero weights leave the cost unchanged."""
+    T = 30
+    sc = oracle.SceneBuf([0, 0, 0.3, 2.0], [10, 5, -3.0, 0.5], [0, 0], np.zeros((0, 4)), T)
+    th = _const_theta(C1, [0.0, 0.0])
+    base = oracle.rollout(C1, sc, th)["cost"]
+    m = oracle.make_model(dict(scenes.C1, goal_heading_weight=0.75, goal_speed_weight=2.0))
+    r = oracle.rollout(m, sc, th)
+    phi_T = r["traj"][-1, 2]                           # 0.3 as the float32 start heading
+    assert phi_T == float(np.float32(0.3)) and r["traj"][-1, 3] == 2.0
+    want = base + 0.75 * (2 * math.pi - 3.0 - phi_T) + 2.0 * 1.5
+    assert abs(r["cost"] - want) < 1e-9
+    m0 = oracle.make_model(dict(scenes.C1, goal_heading_weight=0.0, goal_speed_weight=0.0))
+    assert oracle.rollout(m0, sc, th)["cost"] == base
+
+
 def test_rollout_moving_obstacle_first_collision_step():
     # parked vehicle (u = 0 at a_idle), a point approaching head-on at 2 m/s from 10 m: it
     # crosses the front face (2.25 m) between t = 3.875 s and 3.9 s, so h = 39 is first.
