@@ -103,7 +103,8 @@ def train(prop: Proposal, enc, theta, epochs: int, batch: int = 1024, lr: float 
 
 
 def _diff(a, b):
-    d = a - b
+    with np.errstate(invalid="ignore"):      # inf - inf: both infeasible, counted as equal
+        d = a - b
     d[np.isinf(a) & np.isinf(b)] = 0.0
     return d
 

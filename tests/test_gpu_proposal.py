@@ -1,7 +1,8 @@
 """GPU tests of the learned proposal (through the C-ABI) against the FP64 proposal oracle.
 
 * The BF16 MFMA product: integer-valued bfloat16 operands make every partial sum exact in
-  binary32, so the product must equal the exact one bit for bit in every layout and epilogue;
+  binary32, so the product must equal the exact one bit for bit in every layout, epilogue and
+  split-K slicing;
   real-valued operands stay within the binary32 accumulation bound K 2^-24 sum |a b|.
 * Encoding, forward pass, loss, gradients, Adam step and the Gaussian draws against the oracle,
   each at the GPU's own inputs where rounding decisions could otherwise diverge.
@@ -40,7 +41,8 @@ def bf16_bits(x: np.ndarray) -> torch.Tensor:
 # BF16 MFMA matrix product
 # ------------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("la,lb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (256, 384, 96), (384, 256, 2944)])
+@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (256, 384, 96), (384, 256, 2944),
+                                   (512, 256, 160), (256, 768, 2944)])
 def test_gemm_integer_operands_exact(la, lb, M, N, K):
     say(f"gemm exact: layouts ({la},{lb}), M={M} N={N} K={K}")
     rng = np.random.default_rng([la, lb, M, N, K])
@@ -69,8 +71,9 @@ def test_gemm_integer_operands_exact(la, lb, M, N, K):
     assert np.array_equal(Cf.cpu().numpy().astype(np.float64), np.where(mask > 0, A @ Bk, 0.0))
 
 
-def test_gemm_real_operands_within_accumulation_bound():
-    M, N, K = 256, 256, 2944
+@pytest.mark.parametrize("M,N", [(256, 256), (384, 128)])
+def test_gemm_real_operands_within_accumulation_bound(M, N):
+    K = 2944
     rng = np.random.default_rng(9)
     A = OP.bf16(rng.standard_normal((M, K)))
     B = OP.bf16(rng.standard_normal((N, K)))
