@@ -141,8 +141,15 @@ int nnp_n_theta(const nnp_handle *h);
 /* Step 5 of Alg. 1 as a plain sampler (Sect. II-E): draw N parameter vectors from Philox, roll
  * each over h = 0..T with collision checks of eq. (2) at every h, cost every sample, and return
  * the lowest-cost one (lowest index on ties) with its controls and trajectory. Every sample is
- * simulated over the whole horizon. */
+ * simulated over the whole horizon. The winner's states and controls come from per-sample
+ * records the rollout writes into the handle's workspace (16 N (T+1) + 8 N T bytes, grown on demand like
+ * the extrapolation table) when that size is within the handle's record limit and below 2^31
+ * bytes, else from a re-simulation of the winner; both give the same bits. */
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
+
+/* Largest per-sample record workspace nnp_plan may use (default 2^30 bytes); 0 makes every plan
+ * re-simulate its winner instead. Results do not depend on it. Returns NNP_EINVAL for h == NULL. */
+int nnp_set_record_limit(nnp_handle *h, uint64_t bytes);
 
 /* Many independent problems in one call: the same plan as nnp_plan for every probs[i] (each with
  * its own N, T, P, obstacles, seed and warm start), written to results[i]. All problems are

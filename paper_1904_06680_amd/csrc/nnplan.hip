@@ -9,9 +9,11 @@
 //                          distance) from LDS buffers filled by asynchronous copies, features
 //                          (eq. (3)), MLP (eq. (4)), model (Sect. II-F) and the cost; a u64
 //                          (cost bits, index) atomicMin selects the best sample, lowest index on
-//                          ties.
-//   3. replay_kernel       one workgroup re-simulates the winner with the same device functions
-//                          (points split over 256 lanes) and writes theta*, controls, trajectory.
+//                          ties. When the handle's record limit allows, every sample's states and
+//                          controls are also stored (step-major, coalesced).
+//   3. gather_kernel       copies the winner's records and regenerates theta*; or, without
+//      / replay_kernel     records, one workgroup re-simulates the winner with the same device
+//                          functions (points split over 256 lanes). Both give the same bits.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -36,6 +38,9 @@ constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this 
                                 // subset then come in whole groups of four for K <= 8)
 constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB); 1536 for
                                   // K = 16, so that three workgroups share a CU
+constexpr int BUFFER_RSRC_FLAGS = 0x00020000;   // buffer descriptor word 3: 32-bit data format
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
 
 struct RolloutArgs {
@@ -55,6 +60,8 @@ struct RolloutArgs {
     int P;
     const float *mu, *log_sigma;     // Gaussian proposal for samples [0, n_prop)
     int n_prop;
+    float4 *rec_traj;                // record mode: states [T+1][N] of every sample
+    float2 *rec_ctrl;                //   and controls [T][N] (step-major: coalesced stores)
 };
 
 struct ReplayOut {
@@ -266,6 +273,30 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
     const float oxi = -a.m.oc * a.m.ihl;
     if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TP), wave);
 
+    // Plan-mode records (when a.rec_traj is set) through buffer resources: base and range in
+    // scalar registers, a 32-bit lane offset, the step's offset as a scalar (the host keeps the
+    // records below 2^31 bytes).
+    const bool rec_on = MODE == MODE_PLAN && a.rec_traj != nullptr;
+    const __amdgpu_buffer_rsrc_t rec_t = __builtin_amdgcn_make_buffer_rsrc(
+        a.rec_traj, 0, rec_on ? a.N * (a.T + 1) * 16 : 0, BUFFER_RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rec_c = __builtin_amdgcn_make_buffer_rsrc(
+        a.rec_ctrl, 0, rec_on ? a.N * a.T * 8 : 0, BUFFER_RSRC_FLAGS);
+    // Step h's record: z_h and a_{h-1} (the controls the model applied last, still held for the
+    // features). Issued right after the step's first wait for the copies, so the stores retire
+    // under the point pass instead of delaying the next wait (stores count in vmcnt).
+    auto record = [&](int h) {
+        if (rec_on && active && q == 0) {
+            __builtin_amdgcn_raw_buffer_store_b128(
+                u32x4{__float_as_uint(sim.x), __float_as_uint(sim.y), __float_as_uint(sim.phi),
+                      __float_as_uint(sim.v)},
+                rec_t, sample * 16, h * a.N * 16, 0);
+            if (h > 0)
+                __builtin_amdgcn_raw_buffer_store_b64(
+                    u32x2{__float_as_uint(sim.ap0), __float_as_uint(sim.ap1)}, rec_c, sample * 8,
+                    (h - 1) * a.N * 8, 0);
+        }
+    };
+
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
         const Pose own = sim.begin_step(a.m);
@@ -284,6 +315,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
                 if (t + 1 < ntile)                             // next tile of this step
                     copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TP,
                                        pbuf[(it + 1) & 1], min(TP, P2 - (t + 1) * TP), wave);
+                if constexpr (MODE == MODE_PLAN)
+                    if (t == 0) record(h);
                 if constexpr (K > 1) {
                     if (t == 0) {
                         const v4f p0 = sh.pose[2 * pslot], p1 = sh.pose[2 * pslot + 1];
@@ -318,6 +351,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
             // (issued after the last LDS read of this step, so nothing here waits for it).
             if (h < a.T)
                 copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TP), wave);
+        } else if constexpr (MODE == MODE_PLAN) {
+            record(h);
         }
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
@@ -464,6 +499,47 @@ __global__ __launch_bounds__(BLOCK) void replay_batch_kernel(const RolloutArgs *
     replay_body<NetT, K>(probs[blockIdx.x], outs[blockIdx.x], red, stage);
 }
 
+// The winner's outputs from the records the rollout wrote (the same values the replay computes:
+// the records are the rollout's own states and controls, the cost is the argmin key's).
+template <class NetT>
+__global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, const ReplayOut o)
+{
+    const int tid = threadIdx.x;
+    const unsigned long long key = *a.best_key;
+    int best = (int)(unsigned int)(key & 0xffffffffull);
+    if (key == ~0ull || best >= a.N) best = 0;
+    const float key_cost = __uint_as_float((unsigned int)(key >> 32));
+    for (int h = tid; h <= a.T; h += BLOCK) {
+        const float4 z = a.rec_traj[(size_t)h * a.N + best];
+        if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = z;
+        if (h < a.T) {
+            const float2 c = a.rec_ctrl[(size_t)h * a.N + best];
+            if (o.controls) {
+                o.controls[2 * h] = c.x;
+                o.controls[2 * h + 1] = c.y;
+            }
+            if (o.controls_phys) {
+                o.controls_phys[2 * h] = a.m.delta_max * c.x;
+                o.controls_phys[2 * h + 1] = fmaf(c.y + 1.0f, a.m.u_half_range, a.m.u_min);
+            }
+        } else if (o.goal_reached) {
+            float sv, cv;
+            sincosf(z.z, &sv, &cv);
+            o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi, a.m.eps_v,
+                                                 a.goal, z.x, z.y, z.z, z.w, cv, sv);
+        }
+    }
+    if (tid == 0) {
+        if (o.cost) o.cost[0] = key_cost;
+        if (o.best_index) o.best_index[0] = best;
+        if (o.status) o.status[0] = isinf(key_cost) ? NNP_INFEASIBLE : NNP_OK;
+    }
+    if (o.theta) {
+        const ThetaSource src = make_source<NetT>(a, best);
+        for (int k = tid; k < NetT::NTHETA; k += BLOCK) o.theta[k] = src.one(k);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,
                                                       uint32_t N, uint32_t nt,
                                                       const float *__restrict__ mu,
@@ -494,6 +570,7 @@ struct Variant {
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
     void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, hipStream_t);
     void (*launch_replay_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
+    void (*launch_gather)(const RolloutArgs &, const ReplayOut &, hipStream_t);
 };
 
 template <class NetT, int K>
@@ -529,12 +606,18 @@ void launch_replay_batch_t(const RolloutArgs *probs, const ReplayOut *outs, int 
                        outs);
 }
 
+template <class NetT>
+void launch_gather_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
+{
+    hipLaunchKernelGGL((gather_kernel<NetT>), dim3(1), dim3(BLOCK), 0, s, a, o);
+}
+
 #define NNP_VARIANT(NIN, H1, H2, FEAT, K)                                                         \
     {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, K,                              \
      Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, K>,                  \
      launch_replay_t<Net<NIN, H1, H2, FEAT>, K>,                                                   \
      launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                            \
-     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>}
+     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>, launch_gather_t<Net<NIN, H1, H2, FEAT>>}
 
 const Variant kVariants[] = {
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
@@ -574,6 +657,10 @@ struct nnp_handle {
     unsigned long long *d_key = nullptr;
     float4 *d_ext = nullptr;
     size_t ext_bytes = 0;
+    // per-sample records of nnp_plan (states and controls of every sample)
+    void *d_rec = nullptr;
+    size_t rec_bytes = 0;
+    uint64_t rec_limit = 1ull << 30;
     // batched planning: tables, keys, descriptors (device and pinned host)
     void *d_bext = nullptr, *d_bkeys = nullptr, *d_bmeta = nullptr, *h_bmeta = nullptr;
     size_t bext_bytes = 0, bkeys_bytes = 0, bmeta_bytes = 0, hmeta_bytes = 0;
@@ -861,6 +948,7 @@ void nnp_destroy(nnp_handle *h)
     }
     for (hipEvent_t ev : h->ev_pool) hipEventDestroy(ev);
     if (h->d_ext) hipFree(h->d_ext);
+    if (h->d_rec) hipFree(h->d_rec);
     if (h->d_key) hipFree(h->d_key);
     if (h->d_bext) hipFree(h->d_bext);
     if (h->d_bkeys) hipFree(h->d_bkeys);
@@ -872,6 +960,13 @@ void nnp_destroy(nnp_handle *h)
 
 int nnp_n_theta(const nnp_handle *h) { return h ? h->var->ntheta : NNP_EINVAL; }
 
+int nnp_set_record_limit(nnp_handle *h, uint64_t bytes)
+{
+    if (!h) return NNP_EINVAL;
+    h->rec_limit = bytes;
+    return NNP_OK;
+}
+
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream)
 {
     if (!h) return NNP_EINVAL;
@@ -880,13 +975,25 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
     RolloutArgs a;
     int rc = prepare(h, p, a, s);
     if (rc) return rc;
+    // records of every sample's states and controls when they fit the limit, so that the
+    // winner's outputs are gathered instead of re-simulated
+    const size_t rec_need = (size_t)p->N * (size_t)(p->T + 1) * sizeof(float4) +
+                            (size_t)p->N * (size_t)p->T * sizeof(float2);
+    const bool record = rec_need <= h->rec_limit && rec_need < (1ull << 31);
+    if (record) {
+        rc = grow(h, &h->d_rec, &h->rec_bytes, rec_need, s, "sample records");
+        if (rc) return rc;
+        a.rec_traj = static_cast<float4 *>(h->d_rec);
+        a.rec_ctrl = reinterpret_cast<float2 *>(a.rec_traj + (size_t)p->N * (p->T + 1));
+    }
     rc = launch_rollout(h, a, MODE_PLAN, s);
     if (rc) return rc;
     ReplayOut o = {r->theta, r->controls, r->controls_phys, r->traj, r->cost, r->best_index,
                    r->status, r->goal_reached};
-    h->var->launch_replay(a, o, s);
+    if (record) h->var->launch_gather(a, o, s);
+    else h->var->launch_replay(a, o, s);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(h, e, "replay_kernel launch");
+    if (e != hipSuccess) return hip_fail(h, e, record ? "gather_kernel launch" : "replay_kernel launch");
     h->err.clear();
     return NNP_OK;
 }

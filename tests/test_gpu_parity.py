@@ -289,3 +289,53 @@ def test_goal_heading_and_speed_cost_terms_parity(preset_name):
     ref = oracle.plan(m, ob, N, seed=21)
     say("  argmin:", check_argmin(ref["cost"], int(out["best_index"].item())))
     pl.close()
+
+
+# --------------------------------------------------------------------------------------------
+# Winner outputs: gathered from the rollout's per-sample records, or re-simulated
+# --------------------------------------------------------------------------------------------
+def _plan_both_paths(pl, sc, N, **kw):
+    pl.set_record_limit(1 << 30)
+    rec = np_out(pl.plan(sc, N, **kw))
+    pl.set_record_limit(0)
+    rep = np_out(pl.plan(sc, N, **kw))
+    pl.set_record_limit(1 << 30)
+    return rec, rep
+
+
+@pytest.mark.parametrize("case", ["c0", "c1_full", "infeasible", "paper", "warm", "goal"])
+def test_plan_records_equal_winner_replay(case):
+    """Every output of nnp_plan is the same, bit for bit, whether the winner's states and
+    controls come from the rollout's per-sample records or from re-simulating the winner."""
+    preset = scenes.PAPER if case == "paper" else scenes.C0 if case == "c0" else scenes.C1
+    pl = Planner(preset)
+    kw = dict(seed=3)
+    if case == "c0":
+        sc, N = scenes.scene_c0(1), 1024
+    elif case == "c1_full":
+        sc, N = scenes.scene_c1(1), 65536
+    elif case == "infeasible":
+        sc0 = scenes.scene_c1(0)
+        pts = np.concatenate([sc0.points, [[0.5, 0.2, 0.0, 0.0]]]).astype(np.float32)
+        sc, N = scenes.Scene(sc0.z0, sc0.goal, pts, sc0.T), 1000
+    elif case == "paper":
+        sc, N = scenes.scene_exp5_parking(T=100), 4096
+    elif case == "warm":
+        sc, N = scenes.scene_c1(6), 2048
+        kw["warm_theta"] = pl.sample_theta(1, seed=77, i0=4242)[0].contiguous()
+    else:        # standing start with the goal at the start state: the best sample ends within
+        sc1 = scenes.scene_c1(2)  # the tolerances (goal_reached = 1)
+        z0 = sc1.z0.copy()
+        z0[3] = 0.0
+        sc, N = scenes.Scene(z0, z0.copy(), sc1.points[:0], 20), 4096
+    say(f"records vs replay: {case}, N={N}, T={sc.T}, P={sc.P}")
+    rec, rep = _plan_both_paths(pl, sc, N, **kw)
+    for k in rep:
+        assert np.array_equal(rec[k], rep[k], equal_nan=True), (case, k)
+    say("   best", int(rec["best_index"][0]), "cost", float(rec["cost"][0]), "status",
+        int(rec["status"][0]), "goal_reached", int(rec["goal_reached"][0]))
+    if case == "infeasible":
+        assert rec["status"][0] == NNP_INFEASIBLE
+    if case == "goal":
+        assert rec["goal_reached"][0] == 1
+    pl.close()
