@@ -79,6 +79,16 @@ int nnp_proposal_set_params(nnp_proposal *q, const float *params, void *hip_stre
 /* Copy the current parameters to device params[n_params]. */
 int nnp_proposal_get_params(nnp_proposal *q, float *params, void *hip_stream);
 
+/* Training state, for checkpoint and resume: the parameters and both Adam moments (each device
+ * [n_params] in the parameter layout) and the Adam step count t. get_state copies them out (m or v
+ * may be NULL to skip them; params and step may not). set_state loads all of them, so that the
+ * training steps after it continue bit for bit as they would have without the round trip.
+ * NNP_EINVAL for NULL arguments or a step outside [0, 2^31). */
+int nnp_proposal_get_state(nnp_proposal *q, float *params, float *m, float *v, int64_t *step,
+                           void *hip_stream);
+int nnp_proposal_set_state(nnp_proposal *q, const float *params, const float *m, const float *v,
+                           int64_t step, void *hip_stream);
+
 /* Encodings of `count` problems into device enc[count][72]. Reads z0, goal, a_prev, T, P and obst
  * of each problem (other fields are ignored). count in 1..65535. */
 int nnp_proposal_encode(nnp_proposal *q, const nnp_problem *probs, int count, float *enc,

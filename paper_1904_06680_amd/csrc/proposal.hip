@@ -747,6 +747,47 @@ int nnp_proposal_get_params(nnp_proposal *q, float *params, void *hip_stream)
     return NNP_OK;
 }
 
+int nnp_proposal_get_state(nnp_proposal *q, float *params, float *m, float *v, int64_t *step,
+                           void *hip_stream)
+{
+    if (!q) return NNP_EINVAL;
+    if (!params || !step) return pfail(q, NNP_EINVAL, "null params or step");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipSetDevice(q->device) != hipSuccess) return pfail(q, NNP_EDEVICE, "hipSetDevice failed");
+    const dim3 grid(blocks(q->L.etotal)), block(256);
+    hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, q->params, params, 1);
+    if (m) hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, q->m, m, 1);
+    if (v) hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, q->v, v, 1);
+    if (hipGetLastError() != hipSuccess) return pfail(q, NNP_EDEVICE, "kernel launch failed");
+    *step = q->step;
+    q->err.clear();
+    return NNP_OK;
+}
+
+int nnp_proposal_set_state(nnp_proposal *q, const float *params, const float *m, const float *v,
+                           int64_t step, void *hip_stream)
+{
+    if (!q) return NNP_EINVAL;
+    if (!params || !m || !v) return pfail(q, NNP_EINVAL, "null params, m or v");
+    if (step < 0 || step > INT32_MAX) return pfail(q, NNP_EINVAL, "step out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipSetDevice(q->device) != hipSuccess) return pfail(q, NNP_EDEVICE, "hipSetDevice failed");
+    const size_t bytes = q->L.total * sizeof(float);
+    if (hipMemsetAsync(q->params, 0, bytes, s) != hipSuccess ||
+        hipMemsetAsync(q->m, 0, bytes, s) != hipSuccess ||
+        hipMemsetAsync(q->v, 0, bytes, s) != hipSuccess)
+        return pfail(q, NNP_EDEVICE, "hipMemsetAsync failed");
+    const dim3 grid(blocks(q->L.etotal)), block(256);
+    hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, params, q->params, 0);
+    hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, m, q->m, 0);
+    hipLaunchKernelGGL(pack_kernel, grid, block, 0, s, q->L, v, q->v, 0);
+    refresh_weights(q, s);
+    if (hipGetLastError() != hipSuccess) return pfail(q, NNP_EDEVICE, "kernel launch failed");
+    q->step = (int)step;
+    q->err.clear();
+    return NNP_OK;
+}
+
 int nnp_proposal_encode(nnp_proposal *q, const nnp_problem *probs, int count, float *enc,
                         void *hip_stream)
 {

@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -74,19 +75,40 @@ class Labeller:
 
 
 def train(prop: Proposal, enc, theta, epochs: int, batch: int = 1024, lr: float = 1e-3,
-          seed: int = 0, log=None) -> list:
+          seed: int = 0, log=None, checkpoint: str = "", resume: bool = False,
+          stop_after: int = 0) -> list:
     """Adam on the Gaussian NLL over (enc, theta) pairs; lr drops to 0.3 lr for the last 30% of
-    the epochs. Returns the mean loss per epoch."""
+    the epochs. Returns the mean loss per epoch.
+
+    checkpoint: a file written after every epoch with the network's training state (parameters,
+    Adam moments and step), the shuffling generator's state, the epoch count and the loss history.
+    resume: continue from that file when it exists; the run then ends bit for bit where an
+    uninterrupted run would have (same data, batch, lr, seed and epochs, which are checked).
+    stop_after: end this call after that many epochs (0: none), e.g. to split a run into
+    time-boxed sessions that resume from the checkpoint."""
     torch = prop.torch
     dev = prop._dev()
-    prop.set_params(torch.from_numpy(init_params(prop.n_theta, seed)).to(dev))
     n = enc.shape[0]
     batch = min(batch, n, prop.max_batch)
     loss = torch.empty(1, device=dev)
     acc = torch.zeros(1, device=dev)
     gen = torch.Generator(device="cpu").manual_seed(int(seed))
     hist = []
-    for ep in range(epochs):
+    start = 0
+    run = dict(n=int(n), batch=int(batch), lr=float(lr), seed=int(seed), epochs=int(epochs))
+    if resume and checkpoint and os.path.exists(checkpoint):
+        ck = torch.load(checkpoint, map_location="cpu", weights_only=True)
+        if ck["run"] != run:
+            raise ValueError(f"checkpoint {checkpoint} is of another run: {ck['run']} vs {run}")
+        prop.set_state(ck["state"])
+        gen.set_state(ck["generator"])
+        start, hist = int(ck["epoch"]), [float(x) for x in ck["hist"]]
+        if log:
+            log(f"resumed from {checkpoint} at epoch {start}")
+    else:
+        prop.set_params(torch.from_numpy(init_params(prop.n_theta, seed)).to(dev))
+    end = epochs if stop_after <= 0 else min(epochs, start + stop_after)
+    for ep in range(start, end):
         perm = torch.randperm(n, generator=gen).to(dev)
         acc.zero_()
         steps = 0
@@ -99,6 +121,12 @@ def train(prop: Proposal, enc, theta, epochs: int, batch: int = 1024, lr: float 
         hist.append(float(acc.item()) / max(steps, 1))
         if log and (ep % 5 == 0 or ep == epochs - 1):
             log(f"epoch {ep}: loss {hist[-1]:.2f}")
+        if checkpoint:
+            st = {k: (v.cpu() if hasattr(v, "cpu") else v) for k, v in prop.get_state().items()}
+            tmp = checkpoint + ".tmp"
+            torch.save(dict(run=run, state=st, generator=gen.get_state(), epoch=ep + 1,
+                            hist=hist), tmp)
+            os.replace(tmp, checkpoint)
     return hist
 
 
@@ -172,6 +200,8 @@ def main(argv=None) -> int:
     ap.add_argument("--eval-scenes", type=int, default=256)
     ap.add_argument("--tau", type=float, default=1.0)
     ap.add_argument("--out", default="")
+    ap.add_argument("--checkpoint", default="", help="training state file, written every epoch")
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
     args = ap.parse_args(argv)
     import torch
     t0 = time.time()
@@ -188,7 +218,8 @@ def main(argv=None) -> int:
     keep = torch.isfinite(cost)
     enc, th = enc[keep].contiguous(), th[keep].contiguous()
     log(f"labels: {int(keep.sum())} feasible of {args.labels}")
-    hist = train(prop, enc, th, args.epochs, args.batch, args.lr, log=log)
+    hist = train(prop, enc, th, args.epochs, args.batch, args.lr, log=log,
+                 checkpoint=args.checkpoint, resume=args.resume)
     res = evaluate(lab, args.eval_scenes, scene_seed=2, tau=args.tau, log=log)
     res.update(labels=args.labels, label_samples=args.label_samples, feasible_labels=int(keep.sum()),
                epochs=args.epochs, final_loss=hist[-1])

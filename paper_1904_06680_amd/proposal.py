@@ -11,7 +11,8 @@ import ctypes as C
 from .nnplan import NNP_OK, NnpError, load_library
 
 EXPORTED = ("nnp_proposal_create", "nnp_proposal_destroy", "nnp_proposal_n_params",
-            "nnp_proposal_set_params", "nnp_proposal_get_params", "nnp_proposal_encode",
+            "nnp_proposal_set_params", "nnp_proposal_get_params", "nnp_proposal_get_state",
+            "nnp_proposal_set_state", "nnp_proposal_encode",
             "nnp_proposal_forward", "nnp_proposal_gradients", "nnp_proposal_train_step",
             "nnp_gemm_bf16", "nnp_proposal_last_error")
 
@@ -39,6 +40,8 @@ def lib():
         "nnp_proposal_n_params": (I, [H]),
         "nnp_proposal_set_params": (I, [H, V, V]),
         "nnp_proposal_get_params": (I, [H, V, V]),
+        "nnp_proposal_get_state": (I, [H, V, V, V, C.POINTER(C.c_int64), V]),
+        "nnp_proposal_set_state": (I, [H, V, V, V, C.c_int64, V]),
         "nnp_proposal_encode": (I, [H, V, I, V, V]),
         "nnp_proposal_forward": (I, [H, V, I, V, V, V]),
         "nnp_proposal_gradients": (I, [H, V, V, I, V, V, V]),
@@ -122,6 +125,24 @@ class Proposal:
         out = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self._dev())
         self._check(lib().nnp_proposal_get_params(self.h, _p(out), self._stream()))
         return out
+
+    def get_state(self) -> dict:
+        """Training state: parameters, Adam moments m and v (device tensors) and the step count."""
+        t = self.torch
+        params, m, v = (t.empty(self.n_params, dtype=t.float32, device=self._dev())
+                        for _ in range(3))
+        step = C.c_int64()
+        self._check(lib().nnp_proposal_get_state(self.h, _p(params), _p(m), _p(v),
+                                                  C.byref(step), self._stream()))
+        return dict(params=params, m=m, v=v, step=int(step.value))
+
+    def set_state(self, state: dict):
+        """Load a state from get_state (tensors on any device; copied to this one)."""
+        d = self._dev()
+        ts = [state[k].to(d, self.torch.float32).contiguous() for k in ("params", "m", "v")]
+        self._check(lib().nnp_proposal_set_state(self.h, *(_p(x) for x in ts), int(state["step"]),
+                                                  self._stream()))
+        self.torch.cuda.synchronize(d)
 
     def encode_problems(self, probs):
         """probs: ctypes array of nnplan.nnp_problem (obstacles on this device)."""
