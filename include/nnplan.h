@@ -151,6 +151,13 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
  * re-simulate its winner instead. Results do not depend on it. Returns NNP_EINVAL for h == NULL. */
 int nnp_set_record_limit(nnp_handle *h, uint64_t bytes);
 
+/* Cap on the device workspace the handle grows on demand (extrapolation table, per-sample
+ * records, batch tables and descriptors; default: none). nnp_plan leaves the records out when
+ * they would exceed it; a call that still needs more fails with NNP_ENOMEM before any device work
+ * and names the buffer in nnp_last_error. Lowering the cap frees nothing already allocated.
+ * Returns NNP_EINVAL for h == NULL. */
+int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes);
+
 /* Many independent problems in one call: the same plan as nnp_plan for every probs[i] (each with
  * its own N, T, P, obstacles, seed and warm start), written to results[i]. All problems are
  * rolled out by one launch of one workgroup per (problem, block of samples) item, longest

@@ -661,6 +661,7 @@ struct nnp_handle {
     void *d_rec = nullptr;
     size_t rec_bytes = 0;
     uint64_t rec_limit = 1ull << 30;
+    uint64_t ws_limit = UINT64_MAX;    // cap on the grown device workspace (all buffers above)
     // batched planning: tables, keys, descriptors (device and pinned host)
     void *d_bext = nullptr, *d_bkeys = nullptr, *d_bmeta = nullptr, *h_bmeta = nullptr;
     size_t bext_bytes = 0, bkeys_bytes = 0, bmeta_bytes = 0, hmeta_bytes = 0;
@@ -828,10 +829,19 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
 // Extrapolation-table entries of one problem, with the slack the LDS copies may read past it.
 size_t table_entries(const RolloutArgs &a) { return (size_t)(a.T + 1) * a.P2 + CHUNK; }
 
-// Grow a device buffer (contents are not kept). Synchronises the stream before freeing.
+// Device workspace held by the handle's grown buffers.
+uint64_t workspace_bytes(const nnp_handle *h)
+{
+    return (uint64_t)h->ext_bytes + h->rec_bytes + h->bext_bytes + h->bkeys_bytes + h->bmeta_bytes;
+}
+
+// Grow a device buffer (contents are not kept). Synchronises the stream before freeing. Fails
+// with NNP_ENOMEM, before any device work, when the handle's workspace would exceed its limit.
 int grow(nnp_handle *h, void **buf, size_t *cap, size_t need, hipStream_t s, const char *what)
 {
     if (need <= *cap) return NNP_OK;
+    if (workspace_bytes(h) - *cap + need > h->ws_limit)
+        return fail(h, NNP_ENOMEM, std::string("workspace limit exceeded by the ") + what);
     if (*buf) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
@@ -967,6 +977,13 @@ int nnp_set_record_limit(nnp_handle *h, uint64_t bytes)
     return NNP_OK;
 }
 
+int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes)
+{
+    if (!h) return NNP_EINVAL;
+    h->ws_limit = bytes;
+    return NNP_OK;
+}
+
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream)
 {
     if (!h) return NNP_EINVAL;
@@ -979,7 +996,9 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
     // winner's outputs are gathered instead of re-simulated
     const size_t rec_need = (size_t)p->N * (size_t)(p->T + 1) * sizeof(float4) +
                             (size_t)p->N * (size_t)p->T * sizeof(float2);
-    const bool record = rec_need <= h->rec_limit && rec_need < (1ull << 31);
+    const bool record = rec_need <= h->rec_limit && rec_need < (1ull << 31) &&
+                        workspace_bytes(h) - h->rec_bytes + std::max(rec_need, h->rec_bytes) <=
+                            h->ws_limit;
     if (record) {
         rc = grow(h, &h->d_rec, &h->rec_bytes, rec_need, s, "sample records");
         if (rc) return rc;

@@ -21,7 +21,7 @@ FEAT_PAPER, FEAT_SIX, FEAT_EIGHT = 0, 1, 2
 
 EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_batch", "nnp_rollout",
             "nnp_sample_theta", "nnp_sample_gauss", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
-            "nnp_set_record_limit", "nnp_version")
+            "nnp_set_record_limit", "nnp_set_workspace_limit", "nnp_version")
 
 
 class nnp_model(C.Structure):
@@ -97,6 +97,7 @@ def load_library(path: str = LIB):
         "nnp_last_error": (C.c_char_p, [H]),
         "nnp_set_timing": (C.c_int, [H, C.c_int]),
         "nnp_set_record_limit": (C.c_int, [H, C.c_uint64]),
+        "nnp_set_workspace_limit": (C.c_int, [H, C.c_uint64]),
         "nnp_kernel_time": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
         "nnp_version": (C.c_char_p, []),
     }
@@ -160,6 +161,10 @@ def nnp_set_timing(h, enable: bool) -> int:
 
 def nnp_set_record_limit(h, nbytes: int) -> int:
     return load_library().nnp_set_record_limit(h, int(nbytes))
+
+
+def nnp_set_workspace_limit(h, nbytes: int) -> int:
+    return load_library().nnp_set_workspace_limit(h, int(nbytes))
 
 
 def nnp_kernel_time(h, reset: bool = False):
@@ -436,6 +441,10 @@ class Planner:
     def set_record_limit(self, nbytes: int):
         """Largest per-sample record workspace of plan(); 0 re-simulates every winner."""
         _check(nnp_set_record_limit(self.h, nbytes), self.h)
+
+    def set_workspace_limit(self, nbytes: int):
+        """Cap on the handle's grown device workspace; calls needing more raise (NNP_ENOMEM)."""
+        _check(nnp_set_workspace_limit(self.h, nbytes), self.h)
 
     def kernel_time(self, reset: bool = False):
         rc, ms, n = nnp_kernel_time(self.h, reset)

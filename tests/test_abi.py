@@ -108,4 +108,5 @@ def test_null_arguments():
     assert lib.nnp_sample_theta(0, 0, 0, 0, 10, None, None) == nnplan.NNP_EINVAL
     assert lib.nnp_n_theta(None) == nnplan.NNP_EINVAL
     assert lib.nnp_set_record_limit(None, 0) == nnplan.NNP_EINVAL
+    assert lib.nnp_set_workspace_limit(None, 0) == nnplan.NNP_EINVAL
     lib.nnp_destroy(None)

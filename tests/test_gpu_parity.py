@@ -339,3 +339,75 @@ def test_plan_records_equal_winner_replay(case):
     if case == "goal":
         assert rec["goal_reached"][0] == 1
     pl.close()
+
+
+# --------------------------------------------------------------------------------------------
+# Failure handling and invariances
+# --------------------------------------------------------------------------------------------
+def test_workspace_limit_enomem_and_record_fallback():
+    """A workspace cap below the extrapolation table fails with NNP_ENOMEM before any device
+    work; a cap that holds the table but not the per-sample records falls back to re-simulating
+    the winner, with the same outputs."""
+    from paper_1904_06680_amd.nnplan import NNP_ENOMEM
+    sc = scenes.scene_c1(5)
+    N = 4096
+    ref = np_out(Planner(scenes.C1).plan(sc, N, seed=2))
+    pl = Planner(scenes.C1)
+    pl.set_workspace_limit(1024)
+    with pytest.raises(NnpError) as ei:
+        pl.plan(sc, N, seed=2)
+    assert ei.value.rc == NNP_ENOMEM and "workspace limit" in str(ei.value)
+    pl.set_workspace_limit(2 << 20)        # the 1.2 MB table fits, the 5 MB of records do not
+    got = np_out(pl.plan(sc, N, seed=2))
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    pl.close()
+
+
+def test_nan_parameters_cost_infinity(c1_planner):
+    """Explicit parameters with a NaN give that sample cost +inf (the NaN cost counts as +inf);
+    a NaN warm start is never picked over a feasible sample."""
+    sc = scenes.scene_c1(3)
+    N = 256
+    th = c1_planner.sample_theta(N, seed=4)
+    base = np_out(c1_planner.rollout(sc, N, theta=th, want_traj=False, want_controls=False))
+    th[7, -1] = float("nan")
+    g = np_out(c1_planner.rollout(sc, N, theta=th, want_traj=False, want_controls=False))
+    assert np.isinf(g["cost"][7]) and g["cost"][7] > 0
+    keep = np.arange(N) != 7
+    assert np.array_equal(g["cost"][keep], base["cost"][keep])
+    warm = th[7].contiguous()
+    out = np_out(c1_planner.plan(sc, 2048, seed=1, warm_theta=warm))
+    if out["status"][0] == 0:
+        assert out["best_index"][0] != 0 and np.isfinite(out["cost"][0])
+
+
+def test_rigid_motion_of_the_scene(c1_planner):
+    """Rotating and translating the whole scene (start, goal, points and their velocities) leaves
+    every sample's cost unchanged up to float rounding carried through the closed loop."""
+    sc = scenes.scene_c1(4)                  # 127 of these 1024 samples are feasible
+    N = 1024
+    a, tx, ty = 0.7, 35.0, -20.0
+    R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+
+    def move(z):
+        z = np.asarray(z, np.float64).copy()
+        z[:2] = R @ z[:2] + [tx, ty]
+        z[2] = (z[2] + a + math.pi) % (2 * math.pi) - math.pi
+        return z.astype(np.float32)
+
+    pts = np.asarray(sc.points, np.float64).copy()
+    pts[:, :2] = pts[:, :2] @ R.T + [tx, ty]
+    pts[:, 2:] = pts[:, 2:] @ R.T
+    sc2 = scenes.Scene(move(sc.z0), move(sc.goal), pts.astype(np.float32), sc.T)
+    g1 = np_out(c1_planner.rollout(sc, N, seed=8, want_traj=False, want_controls=False))
+    g2 = np_out(c1_planner.rollout(sc2, N, seed=8, want_traj=False, want_controls=False))
+    c1, c2 = g1["cost"].astype(np.float64), g2["cost"].astype(np.float64)
+    same_feasibility = np.mean(np.isinf(c1) == np.isinf(c2))
+    both = np.isfinite(c1) & np.isfinite(c2)
+    close = np.abs(c1 - c2) <= 1e-3 * np.maximum(np.abs(c1), 1.0)
+    frac_close = float(np.mean(close[both])) if both.any() else 1.0
+    say(f"rigid motion: feasibility agrees on {same_feasibility:.4f}, {both.sum()} feasible in "
+        f"both, costs within 1e-3 on {frac_close:.4f}; best {np.min(c1):.5f} vs {np.min(c2):.5f}")
+    assert both.sum() >= 50 and same_feasibility >= 0.97 and frac_close >= 0.95
+    assert abs(np.min(c1) - np.min(c2)) <= 1e-3 * max(np.min(c1), 1.0)

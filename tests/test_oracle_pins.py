@@ -441,6 +441,20 @@ def test_optional_goal_heading_and_speed_cost_terms():
     assert oracle.rollout(m0, sc, th)["cost"] == base
 
 
+def test_nan_parameters_cost_is_infinite():
+    """A parameter vector with a NaN weight drives the controller, the state and the cost to NaN,
+    and a NaN cost counts as +inf (never selected over a feasible sample); the collision flags
+    stay unset (comparisons with NaN are false)."""
+    T = 20
+    sc = oracle.SceneBuf([0, 0, 0.3, 2.0], [10, 5, 0, 0], [0, 0], [[30.0, 30.0, 0, 0]], T)
+    th = _const_theta(C1, [0.1, 0.2])
+    assert math.isfinite(oracle.rollout(C1, sc, th)["cost"])
+    th[-1] = float("nan")
+    r = oracle.rollout(C1, sc, th)
+    assert math.isinf(r["cost"]) and r["cost"] > 0 and r["first_collision"] == -1
+    assert np.isnan(r["traj"][-1]).any()
+
+
 def test_rollout_moving_obstacle_first_collision_step():
     # parked vehicle (u = 0 at a_idle), a point approaching head-on at 2 m/s from 10 m: it
     # crosses the front face (2.25 m) between t = 3.875 s and 3.9 s, so h = 39 is first.
