@@ -18,7 +18,7 @@ constexpr int ENC_PAD = 128;          // encoding padded with zero columns to a 
 constexpr int HID = NNP_PROP_HIDDEN;
 constexpr int NEAR = NNP_PROP_NEAR;
 constexpr int ROWS = 128;             // batch padding (GEMM tile rows)
-constexpr int COL_CHUNKS = 16;        // row chunks of the bias-gradient column sums
+constexpr int COL_CHUNKS_MAX = 128;   // most row chunks of the bias-gradient column sums
 constexpr float PI_F = 3.14159265358979f;
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -477,7 +477,7 @@ struct nnp_proposal {
           *da1 = nullptr, *partial = nullptr, *loss_tmp = nullptr;
     float *splitk = nullptr;                  // split-K slices of the weight gradients
     size_t splitk_floats = 0;
-    float *colpart = nullptr;                 // column-sum partials [COL_CHUNKS][ny_pad]
+    float *colpart = nullptr;                 // column-sum partials [COL_CHUNKS_MAX][ny_pad]
     // encoding descriptors
     EncProblem *d_enc = nullptr, *h_enc = nullptr;
     int enc_cap = 0;
@@ -518,7 +518,7 @@ int gemm(nnp_proposal *q, int la, int lb, int epi, int M, int N, int K, const ui
     const int tiles = (M / TM) * (N / TN), nkt = K / TK;
     int S = 1;
     if (tiles < 256 && nkt >= 16) {
-        S = std::min(std::min((512 + tiles - 1) / tiles, nkt / 4), 32);
+        S = std::min(std::min((1024 + tiles - 1) / tiles, nkt / 4), 32);
         while (S > 1 && (size_t)S * M * N > q->splitk_floats) --S;
     }
     if (S <= 1) {
@@ -543,14 +543,16 @@ int gemm_splitk(nnp_proposal *q, int la, int lb, int M, int N, int K, const uint
     return gemm(q, la, lb, 0, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, ldc, nullptr, 0, s);
 }
 
-// Column sums over the first B rows in two deterministic passes: COL_CHUNKS row chunks, then the
-// chunk partials in order.
+// Column sums over the first B rows in two deterministic passes: C row chunks (enough
+// workgroups to cover the chip, at least 8 rows each), then the chunk partials in order.
 void colsum(nnp_proposal *q, const float *X, int ld, int B, int N, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(colsum_partial_kernel, dim3(blocks(N), COL_CHUNKS), dim3(256), 0, s, X, ld,
-                       B, N, q->colpart);
-    hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks(N)), dim3(256), 0, s, q->colpart,
-                       COL_CHUNKS, N, out);
+    const int nb = (int)blocks(N);
+    int C = std::max(16, (1024 + nb - 1) / nb);
+    C = std::max(1, std::min(std::min(C, COL_CHUNKS_MAX), B / 8));
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb, C), dim3(256), 0, s, X, ld, B, N,
+                       q->colpart);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3(nb), dim3(256), 0, s, q->colpart, C, N, out);
 }
 
 // Forward pass of B rows (padded to Bp) from enc into the workspace.
@@ -683,7 +685,7 @@ int nnp_proposal_create(nnp_proposal **out, const nnp_proposal_config *c, int de
     q->splitk_floats = (size_t)32 * HID * HID;        // slices of the largest split products
     q->splitk_floats = std::max(q->splitk_floats, (size_t)16 * L.ny_pad * HID);
     if (!rc) rc = alloc(q, &q->splitk, q->splitk_floats);
-    if (!rc) rc = alloc(q, &q->colpart, (size_t)COL_CHUNKS * L.ny_pad);
+    if (!rc) rc = alloc(q, &q->colpart, (size_t)COL_CHUNKS_MAX * L.ny_pad);
     if (rc) {
         nnp_proposal_destroy(q);
         return pfail(nullptr, NNP_ENOMEM, "device allocation failed");
