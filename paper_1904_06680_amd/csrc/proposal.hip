@@ -543,13 +543,13 @@ int gemm_splitk(nnp_proposal *q, int la, int lb, int M, int N, int K, const uint
     return gemm(q, la, lb, 0, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, ldc, nullptr, 0, s);
 }
 
-// Column sums over the first B rows in two deterministic passes: C row chunks (enough
-// workgroups to cover the chip, at least 8 rows each), then the chunk partials in order.
+// Column sums over the first B rows in two deterministic passes: C row chunks of at least 256
+// rows (16 to COL_CHUNKS_MAX of them: more chunks fill the chip for large batches, but the second
+// pass adds the C partials of a column in sequence), then the chunk partials in order.
 void colsum(nnp_proposal *q, const float *X, int ld, int B, int N, float *out, hipStream_t s)
 {
     const int nb = (int)blocks(N);
-    int C = std::max(16, (1024 + nb - 1) / nb);
-    C = std::max(1, std::min(std::min(C, COL_CHUNKS_MAX), B / 8));
+    const int C = std::max(1, std::min(std::max(16, B / 256), std::min(COL_CHUNKS_MAX, B)));
     hipLaunchKernelGGL(colsum_partial_kernel, dim3(nb, C), dim3(256), 0, s, X, ld, B, N,
                        q->colpart);
     hipLaunchKernelGGL(colsum_final_kernel, dim3(nb), dim3(256), 0, s, q->colpart, C, N, out);
