@@ -363,7 +363,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
         }
         if (h < a.T) {
             float a0, a1;
-            sim.advance(a.m, a.goal, md, a0, a1);
+            sim.advance(a.m, a.goal, md, a0, a1, q);
             if constexpr (MODE == MODE_OUT) {
                 if (a.controls && active && q == 0) {
                     float *o = a.controls + ((size_t)sample * a.T + h) * 2;
@@ -456,7 +456,7 @@ __device__ __forceinline__ void replay_body(const RolloutArgs &a, const ReplayOu
                 make_float4(sim.x, sim.y, sim.phi, sim.v);
         if (h < a.T) {
             float a0, a1;
-            sim.advance(a.m, a.goal, md, a0, a1);
+            sim.advance(a.m, a.goal, md, a0, a1, q);
             if (tid == 0) {
                 if (o.controls) {
                     o.controls[2 * h] = a0;

@@ -119,8 +119,20 @@ struct Controller {
     static constexpr int NIN = NetT::NIN, H1 = NetT::H1, H2 = NetT::H2, HL = NetT::HL;
     static constexpr int U1 = H1 / K;
     static constexpr int U2 = H2 ? H2 / K : 1;
-    static constexpr int NO = K == 1 ? 2 : 1;       // output rows held by this lane
+    static constexpr int UL = HL / K;               // inputs of the output layer held by a lane
+    // Output layer: when HL is a multiple of 4, each output is summed in chunks of four inputs
+    // (a multiply and three fused multiply-adds in index order), and the HL / 4 chunk sums are
+    // added pairwise as a balanced tree (chunks 2c and 2c+1 first, then pairs of pairs, ...),
+    // then the bias. A lane holds the output weights of the chunks it covers (one chunk per pair
+    // of lanes at K = 16), computes both outputs, and the tree's upper levels run across lanes;
+    // every lane layout K adds the same numbers in the same tree, so all K give the same bits.
+    // Other widths (K = 1 only) sum in index order starting from the bias.
+    static constexpr bool CHUNKED = HL % 4 == 0;
+    static constexpr int LW = K == 1 ? HL : (UL >= 4 ? UL : 4);   // weights per output per lane
+    static constexpr int NCH = LW / 4;              // chunks summed by one lane (CHUNKED)
+    static constexpr int LPC = UL >= 4 ? 1 : 4 / UL;   // lanes sharing one chunk (K = 16: 2)
     static_assert(H1 % K == 0 && (H2 == 0 || H2 % K == 0), "hidden widths must split over K");
+    static_assert(K == 1 || CHUNKED, "lane layouts need output-layer widths divisible by 4");
     static_assert(K == 1 || ((U1 * NIN) % 4 == 0 && NetT::OFF_B1 % 4 == 0 && U1 % 2 == 0 &&
                              NetT::OFF_WO % 4 == 0 && HL % 4 == 0 &&
                              (H2 == 0 || ((U2 * H1) % 4 == 0 && NetT::OFF_W2 % 4 == 0 &&
@@ -129,7 +141,7 @@ struct Controller {
 
     float w1[U1 * NIN], b1[U1];
     float w2[H2 ? U2 * H1 : 1], b2[U2];
-    float wo[NO * HL], bo[NO];
+    float wo[2][LW], bo[2];
 
     // stage: LDS scratch of ThetaSource::STAGE * block floats shared by the workgroup, each
     // lane using its own column.
@@ -143,8 +155,9 @@ struct Controller {
                 src.template fill_const<NetT::OFF_W2, U2 * H1>(w2);
                 src.template fill_const<NetT::OFF_B2, U2>(b2);
             }
-            src.template fill_const<NetT::OFF_WO, NO * HL>(wo);
-            src.template fill_const<NetT::OFF_BO, NO>(bo);
+            src.template fill_const<NetT::OFF_WO, HL>(wo[0]);
+            src.template fill_const<NetT::OFF_WO + HL, HL>(wo[1]);
+            src.template fill_const<NetT::OFF_BO, 2>(bo);
         } else {
             src.fill_aligned(w1, NetT::OFF_W1 + q * U1 * NIN, stage, tid, block);
             src.fill_even(b1, NetT::OFF_B1 + q * U1);
@@ -152,9 +165,10 @@ struct Controller {
                 src.fill_aligned(w2, NetT::OFF_W2 + q * U2 * H1, stage, tid, block);
                 src.fill_even(b2, NetT::OFF_B2 + q * U2);
             }
-            const int r = q & 1;
-            src.fill_aligned(wo, NetT::OFF_WO + r * HL, stage, tid, block);
-            bo[0] = src.one(NetT::OFF_BO + r);
+            const int e0 = (q / LPC) * LW;          // first output-layer input covered
+            src.fill_aligned(wo[0], NetT::OFF_WO + e0, stage, tid, block);
+            src.fill_aligned(wo[1], NetT::OFF_WO + HL + e0, stage, tid, block);
+            src.fill_even(bo, NetT::OFF_BO);
         }
     }
 
@@ -183,7 +197,68 @@ struct Controller {
         if constexpr (B + 1 < K) accumulate<NOUT, U, B + 1>(W, own, acc);
     }
 
-    __device__ __forceinline__ void forward(const float (&s)[NIN], float &a0, float &a1) const
+    // Pairwise tree over n consecutive chunk sums (n a power of two).
+    template <int N>
+    __device__ __forceinline__ static float tree(const float *v)
+    {
+        if constexpr (N == 1) return v[0];
+        else return tree<N / 2>(v) + tree<N / 2>(v + N / 2);
+    }
+
+    // The upper tree levels across lanes: level l adds the sums of the lane groups whose chunk
+    // sets differ in bit l (exchange patterns: lane ^ 1, lane ^ 2 within a quad, mirrored quads
+    // of a half-row, mirrored half-rows of a row).
+    template <int LEVEL>
+    __device__ __forceinline__ static float cross(float v)
+    {
+        if constexpr (LEVEL == 0) return v + dpp_f<0xB1>(v);
+        else if constexpr (LEVEL == 1) return v + dpp_f<0x4E>(v);
+        else if constexpr (LEVEL == 2) return v + dpp_f<0x141>(v);
+        else return v + dpp_f<0x140>(v);
+    }
+
+    template <int L0, int L1>
+    __device__ __forceinline__ static float cross_levels(float v)
+    {
+        if constexpr (L0 < L1) return cross_levels<L0 + 1, L1>(cross<L0>(v));
+        else return v;
+    }
+
+    static constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+    // Output sums of the chunked layout: the chunks of this lane from its inputs `own`.
+    __device__ __forceinline__ void outputs(const float (&own)[UL], int q, float &o0,
+                                            float &o1) const
+    {
+        float x[LW];
+        if constexpr (UL >= 4) {
+#pragma unroll
+            for (int e = 0; e < LW; ++e) x[e] = own[e];
+        } else {                    // K = 16: the chunk's other two inputs come from lane ^ 1
+            const float p0 = dpp_f<0xB1>(own[0]), p1 = dpp_f<0xB1>(own[1]);
+            const bool odd = q & 1;
+            x[0] = odd ? p0 : own[0];
+            x[1] = odd ? p1 : own[1];
+            x[2] = odd ? own[0] : p0;
+            x[3] = odd ? own[1] : p1;
+        }
+        float c[2][NCH];
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int k = 0; k < NCH; ++k) {
+                float t = wo[o][4 * k] * x[4 * k];
+                t = fmaf(wo[o][4 * k + 1], x[4 * k + 1], t);
+                t = fmaf(wo[o][4 * k + 2], x[4 * k + 2], t);
+                c[o][k] = fmaf(wo[o][4 * k + 3], x[4 * k + 3], t);
+            }
+        constexpr int L0 = ilog2(LPC), L1 = ilog2(K);
+        o0 = cross_levels<L0, L1>(tree<NCH>(c[0])) + bo[0];
+        o1 = cross_levels<L0, L1>(tree<NCH>(c[1])) + bo[1];
+    }
+
+    __device__ __forceinline__ void forward(const float (&s)[NIN], float &a0, float &a1,
+                                            int q) const
     {
         float h1o[U1];
 #pragma unroll
@@ -193,29 +268,29 @@ struct Controller {
             for (int i = 0; i < NIN; ++i) acc = fmaf(w1[u * NIN + i], s[i], acc);
             h1o[u] = tanh_f32(acc);
         }
-        float out[NO];
-#pragma unroll
-        for (int r = 0; r < NO; ++r) out[r] = bo[r];
+        float h2o[U2];
         if constexpr (H2) {
-            float h2o[U2];
 #pragma unroll
             for (int o = 0; o < U2; ++o) h2o[o] = b2[o];
             accumulate<U2, U1>(w2, h1o, h2o);
 #pragma unroll
             for (int o = 0; o < U2; ++o) h2o[o] = tanh_f32(h2o[o]);
-            accumulate<NO, U2>(wo, h2o, out);
-        } else {
-            accumulate<NO, U1>(wo, h1o, out);
         }
+        const float(&hl)[UL] = *reinterpret_cast<const float(*)[UL]>(H2 ? h2o : h1o);
+        float o0, o1;
+        if constexpr (CHUNKED) {
+            outputs(hl, q, o0, o1);
+        } else {
+            o0 = bo[0];
+            o1 = bo[1];
 #pragma unroll
-        for (int r = 0; r < NO; ++r) out[r] = tanh_f32(out[r]);
-        if constexpr (K == 1) {
-            a0 = out[0];
-            a1 = out[1];
-        } else {
-            a0 = dpp_f<0xA0>(out[0]);   // quad_perm [0,0,2,2]: even lane of the pair
-            a1 = dpp_f<0xF5>(out[0]);   // quad_perm [1,1,3,3]: odd lane of the pair
+            for (int j = 0; j < HL; ++j) {
+                o0 = fmaf(wo[0][j], hl[j], o0);
+                o1 = fmaf(wo[1][j], hl[j], o1);
+            }
         }
+        a0 = tanh_f32(o0);
+        a1 = tanh_f32(o1);
     }
 };
 
@@ -353,11 +428,11 @@ struct SampleSim {
     // cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
     // tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
     __device__ __forceinline__ void advance(const DevModel &m, const float (&goal)[4], float md,
-                                            float &a0, float &a1)
+                                            float &a0, float &a1, int q)
     {
         float f[NetT::NIN];
         features(m, goal, md, f);
-        ctl.forward(f, a0, a1);
+        ctl.forward(f, a0, a1, q);
         if (m.rate > 0.0f) a0 = fminf(fmaxf(a0, ap0 - m.rate), ap0 + m.rate);
         const float delta = m.delta_max * a0;
         const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
