@@ -158,7 +158,7 @@ __device__ __forceinline__ float wave_min_f(float v)
 // against one pose. p is the same for the whole wavefront, so every read is an LDS broadcast.
 // Two register groups of G pairs alternate: one is read while the other is tested, so the
 // LDS latency hides behind the arithmetic even at one wavefront per SIMD (G pairs per group:
-// four at one wavefront per SIMD, two when two wavefronts share it). The empty asm
+// four at one or two wavefronts per SIMD, two at three, where registers are short). The empty asm
 // statements consume a group (forcing its wait there), and the scheduling barriers keep the
 // compiler from sinking the reads next to their uses.
 template <int G>
@@ -330,7 +330,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
                     }
                 }
                 const int n_sub = min(TP, P2 - t * TP) / K;   // multiple of 2 (of 4 for K <= 8)
-                point_pass<(K >= 8 ? 2 : 4)>(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
+                point_pass<(K >= 16 ? 2 : 4)>(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
             }
             if constexpr (K > 1) {
                 sh.part[2 * tid] = mm;                     // interleaved (margin, distance)
