@@ -351,7 +351,9 @@ def test_workspace_limit_enomem_and_record_fallback():
     from paper_1904_06680_amd.nnplan import NNP_ENOMEM
     sc = scenes.scene_c1(5)
     N = 4096
-    ref = np_out(Planner(scenes.C1).plan(sc, N, seed=2))
+    pr = Planner(scenes.C1)
+    ref = np_out(pr.plan(sc, N, seed=2))
+    pr.close()
     pl = Planner(scenes.C1)
     pl.set_workspace_limit(1024)
     with pytest.raises(NnpError) as ei:
