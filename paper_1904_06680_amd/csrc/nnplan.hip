@@ -305,7 +305,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
             if constexpr (K > 1) {
                 if (q == 0) {
                     sh.pose[2 * slot] = v4f{own.x, own.y, own.cxi, own.sxi};
-                    sh.pose[2 * slot + 1] = v4f{own.ceta, own.seta, 0.0f, 0.0f};
+                    sh.pose[2 * slot + 1] = v4f{own.ceta, own.nseta, 0.0f, 0.0f};
                 }
             }
             Pose pose = own;
@@ -326,7 +326,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
                         pose.sxi = p0.w;
                         pose.oxi = oxi;
                         pose.ceta = p1.x;
-                        pose.seta = p1.y;
+                        pose.nseta = p1.y;
                     }
                 }
                 const int n_sub = min(TP, P2 - t * TP) / K;   // multiple of 2 (of 4 for K <= 8)

@@ -300,7 +300,7 @@ struct Controller {
 struct Pose {
     float x, y;
     float cxi, sxi, oxi;      // xi' = (c dx + s dy - oc) / hl  = cxi dx + sxi dy + oxi
-    float ceta, seta;         // eta' = (c dy - s dx) / hw     = ceta dy - seta dx
+    float ceta, nseta;        // eta' = (c dy - s dx) / hw     = ceta dy + nseta dx
 
     // Eq. (2) for one extrapolated point, folded into the running minima of the normalised
     // margin max(|xi'|, |eta'|) (< 1 exactly when the point is strictly inside) and of the
@@ -310,7 +310,7 @@ struct Pose {
     {
         const float dx = px - x, dy = py - y;
         const float xi = fmaf(cxi, dx, fmaf(sxi, dy, oxi));
-        const float et = fmaf(ceta, dy, -(seta * dx));
+        const float et = fmaf(ceta, dy, nseta * dx);   // nseta = -seta: a plain multiply
         mg = fmaxf(fabsf(xi), fabsf(et));
         d2 = fmaf(dx, dx, dy * dy);
     }
@@ -382,7 +382,7 @@ struct SampleSim {
         p.sxi = s * m.ihl;
         p.oxi = -m.oc * m.ihl;
         p.ceta = c * m.ihw;
-        p.seta = s * m.ihw;
+        p.nseta = -(s * m.ihw);
         return p;
     }
 
