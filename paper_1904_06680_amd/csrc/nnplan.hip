@@ -161,7 +161,7 @@ __device__ __forceinline__ float wave_min_f(float v)
 // four at one or two wavefronts per SIMD, two at three, where registers are short). The empty asm
 // statements consume a group (forcing its wait there), and the scheduling barriers keep the
 // compiler from sinking the reads next to their uses.
-template <int G>
+template <int G, bool CENTRED>
 __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n, float &mm,
                                            float &md)
 {
@@ -178,7 +178,7 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n
         for (int g = 0; g < G; ++g) b[g] = p[i + G + g];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int g = 0; g < G; ++g) pose.pair(a[g], mm, md);
+        for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (G == 4) asm volatile("" ::"v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
         else asm volatile("" ::"v"(b[0]), "v"(b[1]));
@@ -187,12 +187,12 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n
         for (int g = 0; g < G; ++g) a[g] = p[na + g];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int g = 0; g < G; ++g) pose.pair(b[g], mm, md);
+        for (int g = 0; g < G; ++g) pose.pair<CENTRED>(b[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
     }
     if (i < n) {            // a last group when n is G more than a multiple of 2G
 #pragma unroll
-        for (int g = 0; g < G; ++g) pose.pair(a[g], mm, md);
+        for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
     }
 }
 
@@ -241,7 +241,8 @@ struct RolloutShared {
 };
 
 // The rollout of samples [tile * S, tile * S + S) of one problem by one workgroup.
-template <class NetT, int K, int MODE>
+// CENTRED: the model's rectangle is centred on the reference point (oc = 0); see Pose::point.
+template <class NetT, int K, int MODE, bool CENTRED>
 __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, RolloutShared<K> &sh)
 {
     constexpr int RB = rollout_block(K);
@@ -330,7 +331,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
                     }
                 }
                 const int n_sub = min(TP, P2 - t * TP) / K;   // multiple of 2 (of 4 for K <= 8)
-                point_pass<(K >= 16 ? 2 : 4)>(pose, pbuf[it & 1] + psub * n_sub, n_sub, mm, md);
+                point_pass<(K >= 16 ? 2 : 4), CENTRED>(pose, pbuf[it & 1] + psub * n_sub, n_sub,
+                                                       mm, md);
             }
             if constexpr (K > 1) {
                 sh.part[2 * tid] = mm;                     // interleaved (margin, distance)
@@ -391,26 +393,26 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
 }
 
 
-template <class NetT, int K, int MODE>
+template <class NetT, int K, int MODE, bool CENTRED>
 __global__ __launch_bounds__(rollout_block(K))
 __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_kernel(const RolloutArgs a)
 {
     __shared__ RolloutShared<K> sh;
-    rollout_tile<NetT, K, MODE>(a, blockIdx.x, sh);
+    rollout_tile<NetT, K, MODE, CENTRED>(a, blockIdx.x, sh);
 }
 
 // Many problems of uneven size in one launch: one workgroup per work item (problem, tile of S
 // samples). The host writes the items longest problems first and the dispatcher starts
 // workgroups in grid order, so short problems fill the tail. The item index comes from
 // blockIdx, so the problem descriptor is read with scalar loads, like a kernel argument.
-template <class NetT, int K>
+template <class NetT, int K, bool CENTRED>
 __global__ __launch_bounds__(rollout_block(K))
 __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_batch_kernel(
     const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items)
 {
     __shared__ RolloutShared<K> sh;
     const int2 item = items[blockIdx.x];
-    rollout_tile<NetT, K, MODE_PLAN>(probs[item.x], item.y, sh);
+    rollout_tile<NetT, K, MODE_PLAN, CENTRED>(probs[item.x], item.y, sh);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -568,7 +570,8 @@ struct Variant {
     int n_layers, feature_set, K, ntheta;
     void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
-    void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, hipStream_t);
+    void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, bool centred,
+                                 hipStream_t);
     void (*launch_replay_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
     void (*launch_gather)(const RolloutArgs &, const ReplayOut &, hipStream_t);
 };
@@ -576,12 +579,16 @@ struct Variant {
 template <class NetT, int K>
 void launch_rollout_t(const RolloutArgs &a, int mode, dim3 grid, hipStream_t s)
 {
-    if (mode == MODE_PLAN)
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN>), grid, dim3(rollout_block(K)), 0,
-                           s, a);
+    const dim3 block(rollout_block(K));
+    const bool centred = a.m.oc == 0.0f;
+    if (mode == MODE_PLAN && centred)
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN, true>), grid, block, 0, s, a);
+    else if (mode == MODE_PLAN)
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN, false>), grid, block, 0, s, a);
+    else if (centred)
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT>), grid, dim3(rollout_block(K)), 0,
-                           s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT, false>), grid, block, 0, s, a);
 }
 
 template <class NetT, int K>
@@ -592,10 +599,14 @@ void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
 
 template <class NetT, int K>
 void launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items,
-                            hipStream_t s)
+                            bool centred, hipStream_t s)
 {
-    hipLaunchKernelGGL((rollout_batch_kernel<NetT, K>), dim3(n_items), dim3(rollout_block(K)), 0,
-                       s, probs, items);
+    if (centred)
+        hipLaunchKernelGGL((rollout_batch_kernel<NetT, K, true>), dim3(n_items),
+                           dim3(rollout_block(K)), 0, s, probs, items);
+    else
+        hipLaunchKernelGGL((rollout_batch_kernel<NetT, K, false>), dim3(n_items),
+                           dim3(rollout_block(K)), 0, s, probs, items);
 }
 
 template <class NetT, int K>
@@ -1107,7 +1118,7 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
     hipLaunchKernelGGL(extrapolate_batch_kernel, dim3(64, count), dim3(BLOCK), 0, s, d_args);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "extrapolate_batch_kernel launch");
-    h->var->launch_rollout_batch(d_args, d_items, n_items, s);
+    h->var->launch_rollout_batch(d_args, d_items, n_items, h->dm.oc == 0.0f, s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "rollout_batch_kernel launch");
     h->var->launch_replay_batch(d_args, d_outs, count, s);
