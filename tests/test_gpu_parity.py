@@ -104,6 +104,27 @@ def test_c1_reduced_n_parity(c1_planner, seed):
     assert st["ill_conditioned"] <= 0.2 * N, st
 
 
+def test_c1_offset_rectangle_parity():
+    """The 8-32-32-2 network with a rectangle not centred on the reference point (front 2.6 m,
+    rear 1.9 m), i.e. the general kernels instead of the centred specialisation, every lane
+    layout: per-sample parity with the oracle and identical bits across K."""
+    preset = dict(scenes.C1, front=2.6, rear=1.9)
+    sc = scenes.scene_c1(4)
+    N = 512
+    say(f"C1 offset rectangle: scene 4, N={N}, T={sc.T}, P={sc.P}")
+    outs = []
+    for K in (4, 8, 16):
+        pl = Planner(preset, lanes_per_sample=K)
+        outs.append(np_out(pl.rollout(sc, N, seed=11)))
+        pl.close()
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert np.array_equal(o[k], outs[0][k]), k
+    st = check_samples(preset, sc, outs[1], np.arange(N), 11)
+    say("  ", st)
+    assert st["ill_conditioned"] <= 0.2 * N, st
+
+
 def test_c1_full_size_sampled(c1_planner):
     """N = 65536, T = 50, P = 3000 in the benchmark's launch configuration: 192 random samples
     and the 64 lowest GPU costs are recomputed by the oracle; the plan's argmin, cost and
