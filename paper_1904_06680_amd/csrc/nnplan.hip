@@ -154,28 +154,30 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
-// The obstacle pass of one lane: n consecutive point pairs p[0..n) in LDS (n a multiple of 4)
-// against one pose. p is the same for the whole wavefront, so every read is an LDS broadcast.
+// The obstacle pass of one lane: n point pairs p[0], p[STRIDE], ..., p[(n - 1) STRIDE] in LDS
+// (n a multiple of G) against one pose. The K lanes of a sample take every K-th pair from
+// consecutive start pairs, so one wavefront instruction reads K consecutive pairs (K x 16 bytes
+// on distinct banks), each broadcast to the 64 / K samples of the wavefront.
 // Two register groups of G pairs alternate: one is read while the other is tested, so the
 // LDS latency hides behind the arithmetic even at one wavefront per SIMD (G pairs per group:
 // four at one or two wavefronts per SIMD, two at three, where registers are short). The empty asm
 // statements consume a group (forcing its wait there), and the scheduling barriers keep the
 // compiler from sinking the reads next to their uses.
-template <int G, bool CENTRED>
+template <int G, bool CENTRED, int STRIDE>
 __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n, float &mm,
                                            float &md)
 {
     static_assert(G == 2 || G == 4, "groups of two or four pairs");
     v4f a[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) a[g] = p[g];
+    for (int g = 0; g < G; ++g) a[g] = p[g * STRIDE];
     int i = 0;
     for (; i + 2 * G <= n; i += 2 * G) {
         if constexpr (G == 4) asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]));
         else asm volatile("" ::"v"(a[0]), "v"(a[1]));
         v4f b[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) b[g] = p[i + G + g];
+        for (int g = 0; g < G; ++g) b[g] = p[(i + G + g) * STRIDE];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
@@ -184,7 +186,7 @@ __device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n
         else asm volatile("" ::"v"(b[0]), "v"(b[1]));
         const int na = i + 2 * G < n ? i + 2 * G : i;
 #pragma unroll
-        for (int g = 0; g < G; ++g) a[g] = p[na + g];
+        for (int g = 0; g < G; ++g) a[g] = p[(na + g) * STRIDE];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) pose.pair<CENTRED>(b[g], mm, md);
@@ -218,13 +220,13 @@ __device__ __forceinline__ void wait_copies()
 // ---------------------------------------------------------------------------------------------
 // 2. The rollout of every sample.
 //
-// A workgroup of RB = rollout_block(K) threads holds S = RB / K samples. For the controller a sample occupies K adjacent lanes
-// (its weights are split over them); for the obstacle pass every lane takes one sample and one
-// K-th of the points: lane t tests sample t % S against point subset t / S, which is the same
-// for the whole wavefront. Each step's extrapolated points stream into one of two LDS buffers
-// (at most TILE_PAIRS pairs at a time) while the previous buffer is being tested. Poses go out
-// and per-subset minima come back through LDS (none of that when K = 1, where both layouts
-// coincide).
+// A workgroup of RB = rollout_block(K) threads holds S = RB / K samples; a sample occupies K
+// adjacent lanes of one wavefront, which split its weights for the controller and its points for
+// the obstacle pass: lane q of a sample tests pairs q, q + K, q + 2K, ... of every tile against
+// the sample's own pose (every lane holds the sample's state), and the K partial minima meet
+// through DPP (exact mins: the result does not depend on K). Each step's extrapolated points
+// stream into one of two LDS buffers (at most TILE_PAIRS pairs at a time) while the other one is
+// being tested; one barrier per tile publishes a buffer and frees the other.
 // ---------------------------------------------------------------------------------------------
 constexpr int rollout_block(int K) { return K == 8 ? 512 : 256; }
 constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
@@ -234,10 +236,8 @@ constexpr int rollout_waves_per_eu(int K) { return K >= 16 ? 3 : 1; }
 // LDS of one rollout workgroup.
 template <int K>
 struct RolloutShared {
-    static constexpr int RB = rollout_block(K), S = RB / K, TP = tile_pairs(K);
+    static constexpr int TP = tile_pairs(K);
     v4f pbuf[2][TP];                 // point pairs of the current / next tile
-    v4f pose[2 * S];                 // poses out (two float4 per sample)
-    float part[2 * RB];              // per-subset minima back
 };
 
 // The rollout of samples [tile * S, tile * S + S) of one problem by one workgroup.
@@ -249,19 +249,16 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
     constexpr int S = RB / K;
     constexpr int WAVES = RB / 64;
     constexpr int TP = tile_pairs(K);
-    static_assert(S % 16 == 0, "point subsets must be whole DPP rows");
     static_assert(ThetaSource::STAGE * RB <= 8 * TP, "weight staging fits the buffers");
     auto &pbuf = sh.pbuf;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int q = (tid & 63) % K;
-    const int slot = tid / K;                                  // controller layout
+    const int slot = tid / K;
     const int sample = tile * S + slot;
     const bool active = sample < a.N;
     const int si = active ? sample : a.N - 1;
-    const int pslot = tid % S;                                 // obstacle-pass layout
-    const int psub = tid / S;
 
     SampleSim<NetT, K> sim;
     sim.ctl.load(make_source<NetT>(a, si), q, reinterpret_cast<float *>(&pbuf[0][0]), tid, RB);
@@ -271,7 +268,6 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
     const int P2 = a.P2;
     const int ntile = (P2 + TP - 1) / TP;                      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
-    const float oxi = -a.m.oc * a.m.ihl;
     if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TP), wave);
 
     // Plan-mode records (when a.rec_traj is set) through buffer resources: base and range in
@@ -300,62 +296,28 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
 
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
-        const Pose own = sim.begin_step(a.m);
+        const Pose pose = sim.begin_step(a.m);
         float mm = INFINITY, md = INFINITY;
-        if (ntile > 0) {
-            if constexpr (K > 1) {
-                if (q == 0) {
-                    sh.pose[2 * slot] = v4f{own.x, own.y, own.cxi, own.sxi};
-                    sh.pose[2 * slot + 1] = v4f{own.ceta, own.nseta, 0.0f, 0.0f};
-                }
-            }
-            Pose pose = own;
-            for (int t = 0; t < ntile; ++t, ++it) {
-                wait_copies();
-                __syncthreads();                               // buffer it & 1 (and poses) ready
-                if (t + 1 < ntile)                             // next tile of this step
-                    copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TP,
-                                       pbuf[(it + 1) & 1], min(TP, P2 - (t + 1) * TP), wave);
-                if constexpr (MODE == MODE_PLAN)
-                    if (t == 0) record(h);
-                if constexpr (K > 1) {
-                    if (t == 0) {
-                        const v4f p0 = sh.pose[2 * pslot], p1 = sh.pose[2 * pslot + 1];
-                        pose.x = p0.x;
-                        pose.y = p0.y;
-                        pose.cxi = p0.z;
-                        pose.sxi = p0.w;
-                        pose.oxi = oxi;
-                        pose.ceta = p1.x;
-                        pose.nseta = p1.y;
-                    }
-                }
-                const int n_sub = min(TP, P2 - t * TP) / K;   // multiple of 2 (of 4 for K <= 8)
-                point_pass<(K >= 16 ? 2 : 4), CENTRED>(pose, pbuf[it & 1] + psub * n_sub, n_sub,
-                                                       mm, md);
-            }
-            if constexpr (K > 1) {
-                sh.part[2 * tid] = mm;                     // interleaved (margin, distance)
-                sh.part[2 * tid + 1] = md;
-                __syncthreads();
-                const float2 *pp = reinterpret_cast<const float2 *>(sh.part) + slot;
-                float2 v = pp[0];
-                mm = v.x;
-                md = v.y;
-#pragma unroll
-                for (int r = 1; r < K; ++r) {
-                    v = pp[r * S];                         // one base register, immediate offsets
-                    mm = fminf(mm, v.x);
-                    md = fminf(md, v.y);
-                }
-            }
-            // The next step's first tile streams in while the controller and the model run
-            // (issued after the last LDS read of this step, so nothing here waits for it).
-            if (h < a.T)
-                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[it & 1], min(P2, TP), wave);
-        } else if constexpr (MODE == MODE_PLAN) {
-            record(h);
+        for (int t = 0; t < ntile; ++t, ++it) {
+            wait_copies();
+            __syncthreads();            // buffer it & 1 ready; everyone is done with the other
+            // the next tile in sequence streams into the other buffer: tile t + 1 of this step,
+            // else the first tile of the next step
+            if (t + 1 < ntile)
+                copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TP,
+                                   pbuf[(it + 1) & 1], min(TP, P2 - (t + 1) * TP), wave);
+            else if (h < a.T)
+                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[(it + 1) & 1], min(P2, TP),
+                                   wave);
+            if constexpr (MODE == MODE_PLAN)
+                if (t == 0) record(h);
+            const int n_sub = min(TP, P2 - t * TP) / K;       // multiple of 2 (of 4 for K <= 8)
+            point_pass<(K >= 16 ? 2 : 4), CENTRED, K>(pose, pbuf[it & 1] + q, n_sub, mm, md);
         }
+        if constexpr (MODE == MODE_PLAN)
+            if (ntile == 0) record(h);
+        mm = group_min<K>(mm);
+        md = group_min<K>(md);
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
             if (a.traj && active && q == 0) {
