@@ -70,3 +70,37 @@ def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: in
         except (OSError, ValueError):
             pass
     return dict(res, cached=False)
+
+
+def main(argv=None) -> int:
+    """Tune the lane layout on the seeded 256-problem uneven batch (`scenes.batch_c2`) and print
+    the timings; `--plans n` then plans that batch n more times with the chosen layout (the
+    command a kernel trace of the batched path runs)."""
+    import argparse
+
+    import torch
+
+    from . import scenes
+    ap = argparse.ArgumentParser(description="lane-layout autotuner on the uneven C2 batch")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--plans", type=int, default=0)
+    ap.add_argument("--cache", default="")
+    args = ap.parse_args(argv)
+    scs, Ns, seeds = scenes.batch_c2(args.seed)
+    res = tune_batch(scenes.C1, scs, Ns, seeds, cache=args.cache or None)
+    print(json.dumps(res), flush=True)
+    if args.plans > 0:
+        pl = Planner(scenes.C1, lanes_per_sample=res["lanes_per_sample"])
+        probs, keep = pl.batch_problems(scs, Ns, seeds)
+        outs = [pl.alloc_result(sc.T) for sc in scs]
+        for i in range(args.plans):
+            pl.plan_batch_async(probs, outs)
+            torch.cuda.synchronize(pl._dev())
+            print(json.dumps({"plan": i}), flush=True)
+        del keep
+        pl.close()
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
