@@ -234,16 +234,22 @@ constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
 constexpr int rollout_waves_per_eu(int K) { return K >= 16 ? 3 : 1; }
 
 // LDS of one rollout workgroup.
-template <int K>
+template <class NetT, int K>
 struct RolloutShared {
     static constexpr int TP = tile_pairs(K);
+    // Hidden-layer slots, one per sample, ACT floats each at a stride padded by four floats so
+    // that the float4 reads of the slots in one wavefront start on different banks.
+    static constexpr int ACT = Controller<NetT, K>::ACT;
+    static constexpr int ACT_STRIDE = ACT ? ACT + 4 : 0;
     v4f pbuf[2][TP];                 // point pairs of the current / next tile
+    float act[ACT ? rollout_block(K) / K * ACT_STRIDE : 4];
 };
 
 // The rollout of samples [tile * S, tile * S + S) of one problem by one workgroup.
 // CENTRED: the model's rectangle is centred on the reference point (oc = 0); see Pose::point.
 template <class NetT, int K, int MODE, bool CENTRED>
-__device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, RolloutShared<K> &sh)
+__device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
+                                             RolloutShared<NetT, K> &sh)
 {
     constexpr int RB = rollout_block(K);
     constexpr int S = RB / K;
@@ -327,7 +333,9 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile, Rol
         }
         if (h < a.T) {
             float a0, a1;
-            sim.advance(a.m, a.goal, md, a0, a1, q);
+            constexpr int ACT_STRIDE = RolloutShared<NetT, K>::ACT_STRIDE;
+            sim.template advance<(ACT_STRIDE > 0)>(a.m, a.goal, md, a0, a1, q,
+                                                   sh.act + slot * ACT_STRIDE);
             if constexpr (MODE == MODE_OUT) {
                 if (a.controls && active && q == 0) {
                     float *o = a.controls + ((size_t)sample * a.T + h) * 2;
@@ -359,7 +367,7 @@ template <class NetT, int K, int MODE, bool CENTRED>
 __global__ __launch_bounds__(rollout_block(K))
 __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_kernel(const RolloutArgs a)
 {
-    __shared__ RolloutShared<K> sh;
+    __shared__ RolloutShared<NetT, K> sh;
     rollout_tile<NetT, K, MODE, CENTRED>(a, blockIdx.x, sh);
 }
 
@@ -372,7 +380,7 @@ __global__ __launch_bounds__(rollout_block(K))
 __attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_batch_kernel(
     const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items)
 {
-    __shared__ RolloutShared<K> sh;
+    __shared__ RolloutShared<NetT, K> sh;
     const int2 item = items[blockIdx.x];
     rollout_tile<NetT, K, MODE_PLAN, CENTRED>(probs[item.x], item.y, sh);
 }

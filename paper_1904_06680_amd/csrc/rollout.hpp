@@ -197,6 +197,47 @@ struct Controller {
         if constexpr (B + 1 < K) accumulate<NOUT, U, B + 1>(W, own, acc);
     }
 
+    // Hidden layer 2 may take its input vector through LDS instead of by broadcasts: every lane
+    // writes its U elements to the sample's slot (H1 floats), then reads the whole vector back
+    // four elements at a time. The K lanes sit in one wavefront, whose LDS accesses are carried
+    // out in issue order, so only the compiler has to be kept from moving them. Used for K >= 8,
+    // whose broadcasts are LDS swizzles or DPP row broadcasts (K = 4 broadcasts by quad
+    // permutes, cheaper than the exchange).
+    static constexpr bool LDS_X = K >= 8 && H2 > 0 && U1 % 2 == 0 && H1 % 4 == 0;
+    static constexpr int ACT = LDS_X ? H1 : 0;      // floats of one sample's slot
+
+    // acc[o] += sum_j W[o][j] x[j] as in accumulate, x exchanged through the slot act.
+    template <int NOUT, int U>
+    __device__ __forceinline__ static void accumulate_lds(const float *W, const float (&own)[U],
+                                                          float (&acc)[NOUT], float *act, int q)
+    {
+        constexpr int NINP = U * K;
+        static_assert(U % 2 == 0 && NINP % 4 == 0, "whole float2 writes and float4 reads");
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // last step's reads first
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (U % 4 == 0) {
+#pragma unroll
+            for (int c = 0; c < U / 4; ++c)
+                *reinterpret_cast<float4 *>(act + q * U + 4 * c) =
+                    make_float4(own[4 * c], own[4 * c + 1], own[4 * c + 2], own[4 * c + 3]);
+        } else {
+            *reinterpret_cast<float2 *>(act + q * U) = make_float2(own[0], own[1]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int c = 0; c < NINP / 4; ++c) {
+            const float4 x4 = *reinterpret_cast<const float4 *>(act + 4 * c);
+            const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o)
+                    acc[o] = fmaf(W[o * NINP + 4 * c + u], xs[u], acc[o]);
+        }
+    }
+
     // Pairwise tree over n consecutive chunk sums (n a power of two).
     template <int N>
     __device__ __forceinline__ static float tree(const float *v)
@@ -257,8 +298,10 @@ struct Controller {
         o1 = cross_levels<L0, L1>(tree<NCH>(c[1])) + bo[1];
     }
 
+    // XLDS: hidden layer 2 takes its input through the LDS slot act (LDS_X layouts only).
+    template <bool XLDS = false>
     __device__ __forceinline__ void forward(const float (&s)[NIN], float &a0, float &a1,
-                                            int q) const
+                                            int q, float *act = nullptr) const
     {
         float h1o[U1];
 #pragma unroll
@@ -272,7 +315,8 @@ struct Controller {
         if constexpr (H2) {
 #pragma unroll
             for (int o = 0; o < U2; ++o) h2o[o] = b2[o];
-            accumulate<U2, U1>(w2, h1o, h2o);
+            if constexpr (XLDS && LDS_X) accumulate_lds<U2, U1>(w2, h1o, h2o, act, q);
+            else accumulate<U2, U1>(w2, h1o, h2o);
 #pragma unroll
             for (int o = 0; o < U2; ++o) h2o[o] = tanh_f32(h2o[o]);
         }
@@ -432,12 +476,13 @@ struct SampleSim {
     // Controller, rate limit, control map, one explicit Euler step of the kinematic model.
     // cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
     // tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
+    template <bool XLDS = false>
     __device__ __forceinline__ void advance(const DevModel &m, const float (&goal)[4], float md,
-                                            float &a0, float &a1, int q)
+                                            float &a0, float &a1, int q, float *act = nullptr)
     {
         float f[NetT::NIN];
         features(m, goal, md, f);
-        ctl.forward(f, a0, a1, q);
+        ctl.template forward<XLDS>(f, a0, a1, q, act);
         if (m.rate > 0.0f) a0 = fminf(fmaxf(a0, ap0 - m.rate), ap0 + m.rate);
         const float delta = m.delta_max * a0;
         const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
