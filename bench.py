@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,10 +43,15 @@ def algorithmic_flops(N: int, T: int, P: int, widths) -> float:
 
 
 def source_hash() -> str:
+    """Hash of the rollout kernels' code (csrc/nnplan.hip, rollout.hpp, philox.hpp) with comments
+    and blank lines removed, so that edits to comments leave it unchanged."""
     h = hashlib.sha256()
     for f in ("nnplan.hip", "rollout.hpp", "philox.hpp"):
-        with open(os.path.join(ROOT, "paper_1904_06680_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_06680_amd", "csrc", f), encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -2,11 +2,14 @@
 // Sect. II-E (features eq. (3) -> MLP eq. (4) -> control map and kinematic model of Sect. II-F),
 // the per-point rectangle test of eq. (2) and the cost.
 //
-// Lane layout: a sample occupies K adjacent lanes of a wavefront (K in {1, 2, 4, 8}). Each lane
-// holds H/K rows of every hidden layer plus one row of the output layer, so a 1410-parameter
-// 8-32-32-2 network fits in registers at K = 4. The K lanes split the obstacle points of every
-// step and keep identical copies of the state; hidden activations are all-gathered with DPP lane
-// broadcasts. Every dot product runs over its inputs in index order whatever K is, so results
+// Lane layout: a sample occupies K adjacent lanes of a wavefront (K in {1, 2, 4, 8, 16}). Each
+// lane holds H/K rows of every hidden layer plus the output-layer weights of its own share of the
+// last hidden layer, so the 1410-parameter 8-32-32-2 network fits in registers at K = 8 (178
+// per lane). The K lanes split the obstacle points of every step and keep identical copies of
+// the state; the first hidden layer's outputs reach the second by lane broadcasts (DPP, swizzle)
+// or, for K >= 8 in the rollout kernels, through a per-sample LDS slot, and the output layer's
+// chunk sums meet in a pairwise tree across the lanes. Every hidden-layer dot product runs over
+// its inputs in index order and the output layer uses the same tree whatever K is, so results
 // are bit-identical for every K.
 #pragma once
 
