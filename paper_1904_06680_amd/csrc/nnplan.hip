@@ -225,8 +225,10 @@ __device__ __forceinline__ void wait_copies()
 // the obstacle pass: lane q of a sample tests pairs q, q + K, q + 2K, ... of every tile against
 // the sample's own pose (every lane holds the sample's state), and the K partial minima meet
 // through DPP (exact mins: the result does not depend on K). Each step's extrapolated points
-// stream into one of two LDS buffers (at most TILE_PAIRS pairs at a time) while the other one is
-// being tested; one barrier per tile publishes a buffer and frees the other.
+// stream into one of two LDS buffers (at most tile_pairs(K) pairs at a time) while the other one
+// is being tested; one barrier per tile publishes a buffer and frees the other. For K >= 8 the
+// workgroup's LDS also holds one slot per sample through which the controller's second hidden
+// layer receives its inputs.
 // ---------------------------------------------------------------------------------------------
 constexpr int rollout_block(int K) { return K == 8 ? 512 : 256; }
 constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
