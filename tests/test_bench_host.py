@@ -1,0 +1,52 @@
+"""Host logic of bench.py: the kernel-source hash that guards the committed traffic record, the
+record lookup, and the single-GPU guard."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+from conftest import ROOT
+
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+SRCS = ("nnplan.hip", "rollout.hpp", "philox.hpp")
+
+
+def _tree(tmp_path):
+    d = tmp_path / "paper_1904_06680_amd" / "csrc"
+    d.mkdir(parents=True)
+    for f in SRCS:
+        shutil.copy(os.path.join(ROOT, "paper_1904_06680_amd", "csrc", f), d / f)
+    return d
+
+
+def test_source_hash_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    d = _tree(tmp_path)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash()
+    p = d / "rollout.hpp"
+    text = p.read_text()
+    p.write_text("// a new line comment\n/* a block\n   comment */\n\n" + text + "\n// trailing\n")
+    assert bench.source_hash() == h0
+    p.write_text(text + "\nstatic constexpr int one_more_line = 1;\n")
+    assert bench.source_hash() != h0
+
+
+def test_traffic_record_only_for_the_recorded_sources(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    rec = {"source_hash": "0123456789abcdef", "bytes_per_launch": 12345}
+    (tmp_path / "profiles" / "rollout_c1_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_record("0123456789abcdef") == 12345
+    assert bench.traffic_record("fedcba9876543210") is None
+    (tmp_path / "profiles" / "rollout_c1_traffic.json").write_text("{not json")
+    assert bench.traffic_record("0123456789abcdef") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
