@@ -121,6 +121,35 @@ void orc_mlp(const orc_model *m, const double *theta, const double *s, double *a
     a[1] = x[1];
 }
 
+/* The same controller evaluated at binary32 precision, for the float-rounding mode 3 of
+ * orc_rollout: the inputs, every partial sum of each unit's weighted sum (in index order) and
+ * every activation are rounded to float. This does not reproduce any particular float
+ * implementation bit for bit; it perturbs the controller by errors of the size such an
+ * implementation makes. */
+static double f32r(double v) { return (double)(float)v; }
+
+static void mlp_binary32(const orc_model *m, const double *theta, const double *s, double *a)
+{
+    double x[ORC_MAX_WIDTH], y[ORC_MAX_WIDTH];
+    int n_in = m->widths[0];
+    for (int i = 0; i < n_in; ++i) x[i] = f32r(s[i]);
+    const double *p = theta;
+    for (int l = 0; l < m->n_layers; ++l) {
+        int nin = m->widths[l], nout = m->widths[l + 1];
+        const double *W = p;
+        const double *b = p + (size_t)nout * nin;
+        for (int o = 0; o < nout; ++o) {
+            double acc = f32r(b[o]);
+            for (int i = 0; i < nin; ++i) acc = f32r(acc + W[(size_t)o * nin + i] * x[i]);
+            y[o] = f32r(tanh(acc));
+        }
+        for (int o = 0; o < nout; ++o) x[o] = y[o];
+        p += (size_t)nout * nin + nout;
+    }
+    a[0] = x[0];
+    a[1] = x[1];
+}
+
 /* Heading angles are kept in [-pi, pi). Every difference wrapped here is within one turn of
  * that range, so a single correction suffices. */
 double orc_wrap_angle(double a)
@@ -280,8 +309,9 @@ static int goal_reached(const orc_model *m, const double z[4], const double goal
 /* +inf on any collision. Two optional terms (weights 0 by default) add the terminal heading and */
 /* speed errors to the goal setpoint, for missions whose setpoints prescribe them (Sect. III).   */
 /* fp32_state = 1 rounds the state to float after every step; 2 also rounds the features and the */
-/* applied controls. The tests use the gap to the plain run to recognise samples whose outcome is */
-/* ill-conditioned at float precision.                                                           */
+/* applied controls; 3 in addition evaluates the controller at binary32 precision (mlp_binary32). */
+/* The tests use the gap to the plain run to recognise samples whose outcome is ill-conditioned  */
+/* at float precision.                                                                           */
 /* ------------------------------------------------------------------------------------------ */
 void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, int fp32_state,
                  orc_record *rec)
@@ -325,11 +355,12 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
 
         double s[ORC_MAX_WIDTH], a_raw[2], a[2], delta, u, zn[4];
         orc_features(m, z, sc->goal, d_near, ap, s);
-        if (fp32_state == 2)
+        if (fp32_state >= 2)
             for (int i = 0; i < m->widths[0]; ++i) s[i] = (double)(float)s[i];
-        orc_mlp(m, theta, s, a_raw);
+        if (fp32_state == 3) mlp_binary32(m, theta, s, a_raw);
+        else orc_mlp(m, theta, s, a_raw);
         orc_limit_rate(m, a_raw, ap, a);
-        if (fp32_state == 2) {
+        if (fp32_state >= 2) {
             a[0] = (double)(float)a[0];
             a[1] = (double)(float)a[1];
         }

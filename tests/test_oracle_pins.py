@@ -610,3 +610,165 @@ def test_flags_at_poses_matches_rollout_flags():
     r = oracle.rollout(C1, ob, th)
     fl = oracle.flags_at_poses(C1, ob, r["traj"][:, :3], np.arange(sc.T + 1), 1e-9)
     assert np.array_equal(np.where(fl == 2, r["step_flags"], fl), r["step_flags"])
+
+
+# --------------------------------------------------------------------------------------------
+# The step-at-given-states entry and the float-rounding modes of the rollout
+# --------------------------------------------------------------------------------------------
+def _pin_cases():
+    """(preset, scene, samples): a C0 scene, a C1 scene with moving points (every step's
+    extrapolation differs), the paper preset with its steering-rate limit, and a small scene whose
+    points all move near the vehicle."""
+    c0 = scenes.scene_c0(3)
+    c1 = scenes.scene_c1(2, T=12)
+    paper = scenes.scene_exp5_parking(T=30)
+    moving = scenes.random_scene(np.random.default_rng(3), P=40, T=12, box=8.0, vmax=3.0)
+    return [("c0", scenes.C0, c0, 6), ("c1", scenes.C1, c1, 4), ("paper", scenes.PAPER, paper, 6),
+            ("moving", scenes.C1, moving, 6)]
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 3], ids=["c0", "c1", "paper", "moving"])
+def test_step_at_states_reproduces_rollout(case):
+    """At the oracle's own closed-loop states, one step evaluated at (z_h, a_{h-1}, h) gives back
+    the rollout's next state, applied controls and nearest distance bit for bit. An off-by-one in
+    the step index moves the extrapolated points (C1 has moving points), and a miswired previous
+    control changes the features and the rate limit."""
+    name, preset, sc, n = _pin_cases()[case]
+    m = oracle.make_model(preset)
+    ob = oracle.SceneBuf(sc.z0, sc.goal, sc.a_prev_or_idle(preset), sc.points, sc.T)
+    T = sc.T
+    moved = 0
+    for i in range(n):
+        th = oracle.theta(17, 0, i, 1, oracle.n_theta(m))[0]
+        r = oracle.rollout(m, ob, th)
+        ap = np.concatenate([np.asarray(ob.s.a_prev[:2])[None], r["controls"][:T - 1]], 0)
+        st = oracle.step_at_states(m, ob, th, r["traj"][:T], ap, np.arange(T))
+        assert np.array_equal(st["a"], r["controls"]), name
+        assert np.array_equal(st["z_next"], r["traj"][1:]), name
+        assert np.array_equal(st["d_near"], r["d_near"][:T]), name
+        # the pin is sensitive to the step index and to the previous controls
+        shifted = oracle.step_at_states(m, ob, th, r["traj"][:T], ap, np.arange(1, T + 1))
+        moved += not np.array_equal(shifted["d_near"], r["d_near"][:T])
+        wrong_ap = oracle.step_at_states(m, ob, th, r["traj"][:T], np.roll(ap, 1, 0), np.arange(T))
+        assert not np.array_equal(wrong_ap["a"], r["controls"]), name
+    if name == "moving":
+        assert moved == n
+
+
+def _f32(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
+def _numpy_rollout(preset, sc, th, fp32_state):
+    """Second implementation of a closed-loop rollout, vectorised over samples with numpy (shares
+    nothing with the C oracle), with the oracle's float-rounding modes written from their
+    definition: 1 rounds the state to binary32 after every step; 2 also rounds the feature vector
+    and the applied (rate-limited) controls; 3 also evaluates the controller in binary32 (every
+    partial sum of a unit's weighted sum, in index order, and every activation rounded)."""
+    w = list(preset["widths"])
+    N = len(th)
+    f = lambda v: float(np.float32(v))  # noqa: E731
+    dt, L, lr = f(preset["dt"]), f(preset["lf"]) + f(preset["lr"]), f(preset["lr"])
+    z = np.tile(sc.z0.astype(float), (N, 1))
+    g = sc.goal.astype(float)
+    ap = np.tile(sc.a_prev_or_idle(preset).astype(float), (N, 1))
+    P = sc.points.astype(float)
+    traj = np.empty((N, sc.T + 1, 4))
+    ctrl = np.empty((N, sc.T, 2))
+    first = np.full(N, -1)
+    E = np.zeros(N)
+    rate = f(preset["delta_rate_max"]) * dt / f(preset["delta_max"]) if preset["delta_rate_max"] else 0
+    for h in range(sc.T + 1):
+        traj[:, h] = z
+        q = P[:, :2] + h * dt * P[:, 2:]
+        dx = q[None, :, 0] - z[:, None, 0]
+        dy = q[None, :, 1] - z[:, None, 1]
+        c, s = np.cos(z[:, 2])[:, None], np.sin(z[:, 2])[:, None]
+        xi, eta = c * dx + s * dy, -s * dx + c * dy
+        inside = (xi < f(preset["front"])) & (-xi < f(preset["rear"])) & \
+                 (np.abs(eta) < f(preset["half_width"]))
+        first = np.where((first < 0) & inside.any(1), h, first)
+        if h == sc.T:
+            break
+        dn = np.sqrt((dx * dx + dy * dy).min(1)) if len(P) else np.full(N, np.inf)
+        gx, gy = g[0] - z[:, 0], g[1] - z[:, 1]
+        cc, ss = np.cos(z[:, 2]), np.sin(z[:, 2])
+        e = g[2] - z[:, 2]
+        e = np.where(e >= np.pi, e - 2 * np.pi, np.where(e < -np.pi, e + 2 * np.pi, e))
+        xg, yg = (cc * gx + ss * gy) / f(preset["norm_xi"]), (-ss * gx + cc * gy) / f(preset["norm_eta"])
+        if preset["feature_set"] == scenes.FEAT_PAPER:
+            feats = [xg, yg, e / f(preset["norm_phi"]), (g[3] - z[:, 3]) / f(preset["norm_v"]), ap[:, 0]]
+        else:
+            feats = [xg, yg, e / f(preset["norm_phi"]), z[:, 3] / f(preset["norm_v"]),
+                     np.minimum(dn, f(preset["d_cap"])) / f(preset["d_cap"]), ap[:, 0]]
+            if preset["feature_set"] == scenes.FEAT_EIGHT:
+                feats += [(g[3] - z[:, 3]) / f(preset["norm_v"]), ap[:, 1]]
+        x = np.stack(feats, 1)
+        if fp32_state >= 2:
+            x = _f32(x)
+        off = 0
+        for l in range(len(w) - 1):
+            W = th[:, off:off + w[l + 1] * w[l]].reshape(N, w[l + 1], w[l])
+            off += w[l + 1] * w[l]
+            b = th[:, off:off + w[l + 1]]
+            off += w[l + 1]
+            if fp32_state == 3:          # binary32 sums in index order, binary32 activations
+                acc = _f32(b)
+                for i in range(w[l]):
+                    acc = _f32(acc + W[:, :, i] * x[:, i:i + 1])
+                x = _f32(np.tanh(acc))
+            else:
+                x = np.tanh(np.einsum("noi,ni->no", W, x) + b)
+        a = x.copy()
+        if rate:
+            a[:, 0] = np.clip(a[:, 0], ap[:, 0] - rate, ap[:, 0] + rate)
+        if fp32_state >= 2:
+            a = _f32(a)
+        ctrl[:, h] = a
+        delta = f(preset["delta_max"]) * a[:, 0]
+        u = f(preset["u_min"]) + (a[:, 1] + 1) / 2 * (f(preset["u_max"]) - f(preset["u_min"]))
+        beta = np.arctan(lr * np.tan(delta) / L)
+        v = z[:, 3]
+        nz = np.empty_like(z)
+        nz[:, 0] = z[:, 0] + dt * v * np.cos(z[:, 2] + beta) / np.cos(beta)
+        nz[:, 1] = z[:, 1] + dt * v * np.sin(z[:, 2] + beta) / np.cos(beta)
+        ph = z[:, 2] + dt * v * np.tan(delta) / L
+        nz[:, 2] = np.where(ph >= np.pi, ph - 2 * np.pi, np.where(ph < -np.pi, ph + 2 * np.pi, ph))
+        nz[:, 3] = np.clip(v + dt * u, f(preset["v_min"]), f(preset["v_max"]))
+        E += (a * a).sum(1)
+        z = _f32(nz) if fp32_state else nz
+        ap = a
+    cost = np.hypot(z[:, 0] - g[0], z[:, 1] - g[1]) + f(preset["effort_weight"]) * dt * E
+    cost[first >= 0] = np.inf
+    return dict(traj=traj, controls=ctrl, cost=cost, first_collision=first)
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 3], ids=["c0", "c1", "paper", "moving"])
+def test_rounding_modes_match_numpy_definition(case):
+    """The oracle's float-rounding modes (used by the parity tests to measure how sensitive each
+    sample is to binary32 rounding) against the numpy rollout that applies the same rounding
+    points: every mode agrees to 1e-12, and the modes differ from each other by far more, so a
+    rounding applied at the wrong place or not at all fails."""
+    name, preset, sc, _ = _pin_cases()[case]
+    sc = scenes.Scene(sc.z0, sc.goal, sc.points, min(sc.T, 8))
+    m = oracle.make_model(preset)
+    ob = oracle.SceneBuf(sc.z0, sc.goal, sc.a_prev_or_idle(preset), sc.points, sc.T)
+    N, seed = 24, 4
+    th = oracle.theta(seed, 0, 0, N, oracle.n_theta(m))
+    got, want = {}, {}
+    for mode in (0, 1, 2, 3):
+        got[mode] = oracle.rollout_samples(m, ob, seed, 0, np.arange(N), fp32_state=mode)
+        want[mode] = _numpy_rollout(preset, sc, th, mode)
+        assert np.array_equal(got[mode]["first_collision"], want[mode]["first_collision"]), name
+        assert np.allclose(got[mode]["traj"], want[mode]["traj"], rtol=1e-12, atol=1e-12), name
+        assert np.allclose(got[mode]["controls"], want[mode]["controls"], rtol=1e-12, atol=1e-12)
+        fin = np.isfinite(want[mode]["cost"])
+        assert np.array_equal(fin, np.isfinite(got[mode]["cost"]))
+        assert np.allclose(got[mode]["cost"][fin], want[mode]["cost"][fin], rtol=1e-12)
+    # the rounding points change the results by float-rounding amounts (far above 1e-12)
+    for a, b in ((0, 1), (1, 2), (2, 3)):
+        d = np.abs(got[a]["traj"] - got[b]["traj"]).max()
+        assert 1e-9 < d < 1e-3, (name, a, b, d)
+    # mode 2 rounds the controls: every control it applies is a binary32 value
+    assert np.array_equal(_f32(got[2]["controls"]), got[2]["controls"])
+    assert not np.array_equal(_f32(got[1]["controls"]), got[1]["controls"])
