@@ -147,3 +147,98 @@ def test_fleet_waypoint_switching_and_completion():
     assert s3[1]["steps"] == 3 and not s3[1]["done"]
     fl.close()
     pl.close()
+
+
+def _move_f32(pts, dt):
+    """One sampling time of constant-velocity motion in binary32 with a single rounding (the
+    fleet's fused multiply-add), evaluated exactly in extended precision first."""
+    L = np.longdouble
+    xy = pts[:, :2].astype(L) + L(np.float32(dt)) * pts[:, 2:].astype(L)
+    out = pts.copy()
+    out[:, :2] = xy.astype(np.float32)
+    return out
+
+
+def test_fleet_steps_against_the_oracle():
+    """Three sampling times of Alg. 1 served by the fleet, every step checked against the FP64
+    oracle at the fleet's own state: the plan's argmin over all samples (sample 0 being the
+    warm start theta*_{t-1} from the second step on), its cost, the applied control a_t at z_t,
+    the next state z_{t+1} = model(z_t, a_t), and the waypoint switch by the Table II tolerance
+    test at z_{t+1}. Vehicle 0's first waypoint is its start state (reached after one step, so
+    the goal switches); vehicle 1 drives among moving points."""
+    import oracle
+    from parity import COST_RTOL, CTRL_STEP_ATOL, MODEL_STEP_RTOL, _traj_err, check_argmin
+    preset = scenes.C0
+    T, N, seed, steps = 20, 1024, 5, 3
+    sc0 = scenes.scene_c0(0)
+    z0a = np.zeros(4, np.float32)
+    wpa = np.stack([z0a, sc0.goal]).astype(np.float32)
+    rng = np.random.default_rng(4)
+    pb = np.zeros((150, 4), np.float32)
+    pb[:, :2] = rng.uniform(-25, 25, (150, 2))
+    pb[:, 2:] = rng.uniform(-2, 2, (150, 2))
+    far = np.hypot(pb[:, 0], pb[:, 1]) > 4.0
+    pb = pb[far]
+    z0b = np.array([0.0, 0.0, 0.4, 2.0], np.float32)
+    wpb = np.array([[20.0, 12.0, 0.0, 0.0]], np.float32)
+    vs = [dict(z0=z0a, waypoints=wpa, points=sc0.points.copy()),
+          dict(z0=z0b, waypoints=wpb, points=pb)]
+    pl = Planner(preset)
+    fl = Fleet(pl, dev_points(vs), T=T, n_uniform=N, seed=seed)
+    m = oracle.make_model(preset)
+    nt = oracle.n_theta(m)
+    a_idle = scenes.a_idle(preset)
+    z = [v["z0"].copy() for v in vs]
+    a_prev = [a_idle.copy() for _ in vs]
+    wp = [0 for _ in vs]
+    pts = [v["points"].copy() for v in vs]
+    warm = [None for _ in vs]
+    switched = 0
+    for t in range(steps):
+        fl.step()
+        st = fl.state()
+        for i, v in enumerate(vs):
+            s = st[i]
+            goal = v["waypoints"][wp[i]]
+            ob = oracle.SceneBuf(z[i], goal, a_prev[i], pts[i], T)
+            cost = oracle.rollout_samples(m, ob, seed + i, t, np.arange(N), want_traj=False,
+                                          want_controls=False)["cost"]
+            th0 = oracle.theta(seed + i, t, 0, 1, nt)[0] if warm[i] is None else warm[i]
+            cost[0] = oracle.rollout(m, ob, th0)["cost"]
+            rule = check_argmin(cost, 0 if not np.isfinite(cost).any() else int(np.argmin(cost)))
+            best = int(np.argmin(cost)) if np.isfinite(cost).any() else 0
+            th = th0 if best == 0 else oracle.theta(seed + i, t, best, 1, nt)[0]
+            # the GPU's applied control is the chosen sample's first control at z_t
+            stp = oracle.step_at_states(m, ob, th, z[i][None], a_prev[i][None], [0])
+            ea = np.abs(s["a"].astype(np.float64) - stp["a"][0]).max()
+            c_gpu = float(s["cost"])
+            say(f"step {t} vehicle {i}: oracle best {best} ({rule}) cost {cost[best]:.6f}, "
+                f"gpu cost {c_gpu:.6f}, |a - a_oracle| {ea:.2e}")
+            assert rule == "exact" or rule == "infeasible"
+            if np.isfinite(cost[best]):
+                assert abs(c_gpu - cost[best]) <= COST_RTOL * max(cost[best], 1.0), (t, i)
+            else:
+                assert np.isinf(c_gpu)
+            assert ea <= CTRL_STEP_ATOL, (t, i, s["a"], stp["a"][0])
+            # z_{t+1} is one model step from z_t with the applied control
+            d, u = oracle.control_map(m, s["a"].astype(np.float64))
+            zn = oracle.vehicle_step(m, z[i].astype(np.float64), d, u)
+            assert _traj_err(s["z"].astype(np.float64)[None], zn[None]).max() <= MODEL_STEP_RTOL
+            # waypoint switch: the Table II tolerances at z_{t+1}, in FP64
+            zz = s["z"].astype(np.float64)
+            c, sn = np.cos(zz[2]), np.sin(zz[2])
+            gx, gy = goal[0] - zz[0], goal[1] - zz[1]
+            off = np.array([abs(c * gx + sn * gy) - m.eps_xi, abs(-sn * gx + c * gy) - m.eps_eta,
+                            abs(oracle.wrap_angle(goal[2] - zz[2])) - m.eps_phi,
+                            abs(goal[3] - zz[3]) - m.eps_v])
+            assert np.all(np.abs(off) > 1e-5), off          # decided at binary32 precision
+            reached = bool(np.all(off <= 0))
+            wp[i] += int(reached)
+            switched += int(reached)
+            assert s["waypoint"] == wp[i] and s["steps"] == t + 1, (t, i, s["waypoint"], wp[i])
+            assert s["done"] == (wp[i] >= len(v["waypoints"]))
+            z[i], a_prev[i], warm[i] = s["z"].copy(), s["a"].copy(), th
+            pts[i] = _move_f32(pts[i], preset["dt"])
+    assert switched == 1 and wp[0] == 1
+    fl.close()
+    pl.close()
