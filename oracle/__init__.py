@@ -30,6 +30,21 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+SANITIZE_SRC = os.path.join(_HERE, "sanitize_check.c")
+
+
+def build_sanitized(out_path: str) -> str:
+    """Compile the oracle with its host driver (sanitize_check.c) under AddressSanitizer and
+    UndefinedBehaviorSanitizer into the executable out_path (no OpenMP: one thread, so the
+    sanitizers see every access of the plain code)."""
+    cmd = ["gcc", "-std=c99", "-O1", "-g", "-ffp-contract=off", "-fno-fast-math",
+           "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-Wno-unknown-pragmas", "-o", out_path, SANITIZE_SRC,
+           SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out_path
+
+
 class Model(C.Structure):
     _fields_ = [
         ("dt", C.c_double), ("lf", C.c_double), ("lr", C.c_double),
