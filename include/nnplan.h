@@ -176,16 +176,34 @@ int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes);
 int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_result *results,
                    void *hip_stream);
 
-/* Same rollout kernel as nnp_plan, with per-sample outputs instead of the argmin. theta, if not
- * NULL, is a device [N][n_theta] array of parameters used instead of the Philox draws (explicit-
- * parameter hook for tests and for externally proposed samples); p->warm_theta is ignored then. */
+/* Step 5 of Alg. 1 (Sect. II-E) without the final selection: every sample's closed loop over the
+ * horizon (features eq. (3), controller eq. (4), model eq. (5) of Sect. II-F, obstacle points
+ * extrapolated at constant velocity and tested with eq. (2) at every h = 0..T), with per-sample
+ * outputs instead of the argmin: o->cost[N] (f32, +inf after any collision), o->collided[N]
+ * (i32 0/1), o->first_collision[N] (i32, first step with a point inside, -1 if none),
+ * o->min_margin[N] (f32, smallest normalised margin over steps and points, < 1 inside), and
+ * optionally o->traj[N][T+1][4] (z_h) and o->controls[N][T][2] (normalised a_h). Every output
+ * pointer is a caller-owned device buffer and may be NULL (not written). Same kernel and device
+ * functions as nnp_plan, so the costs are bit-identical to the ones nnp_plan minimises.
+ * theta, if not NULL, is a device [N][n_theta] array of parameters used instead of the Philox
+ * draws (explicit-parameter hook for tests and for externally proposed samples, the theta that
+ * Sect. II-E's fourth comment lists among the host-to-GPU inputs); p->warm_theta is ignored
+ * then. Asynchronous on hip_stream. Returns NNP_OK, NNP_EINVAL (null handle/problem/output
+ * struct, N < 1, T outside 1..4096, P outside 0..2^22, non-finite or out-of-range z0, goal or
+ * a_prev), NNP_ENOMEM (workspace) or NNP_EDEVICE (HIP error; nnp_last_error has the text). */
 int nnp_rollout(nnp_handle *h, const nnp_problem *p, const float *theta, nnp_rollout_out *o,
                 void *hip_stream);
 
-/* The parameter draws of nnp_plan for samples i0..i0+N-1 into device out[N][n_theta]:
- * theta_k of sample i = (2m + 1 - 2^24) 2^-24, m the top 24 bits of word k mod 4 of
- * Philox4x32-10(counter = (k / 4, i, 0, inst), key = (seed low 32, seed high 32)). Runs on the
- * current HIP device. */
+/* The parameter draws of nnp_plan for samples i0..i0+N-1 into device out[N][n_theta]. Sect.
+ * II-E's fourth comment has the host pass the parameter samples and the current random seed to
+ * the GPU at every sampling time; here the samples are a pure function of (seed, inst, i), so
+ * only the seed crosses, and this call materialises the same values: theta_k of sample i =
+ * (2m + 1 - 2^24) 2^-24, m the top 24 bits of word k mod 4 of Philox4x32-10(counter = (k / 4,
+ * i, 0, inst), key = (seed low 32, seed high 32)), i.e. uniform in (-1, 1) (the reading of the
+ * unbounded parameter range of Sect. III-A as the uniform box the plain sampler draws from),
+ * exact in binary32. out is caller-owned; layout sample-major, parameters layer by layer (W_l
+ * row-major, then b_l). Asynchronous on hip_stream, on the current HIP device. Returns NNP_OK,
+ * NNP_EINVAL (out == NULL, N == 0, n_theta == 0 or N * n_theta >= 2^40) or NNP_EDEVICE. */
 int nnp_sample_theta(uint64_t seed, uint32_t inst, uint32_t i0, uint32_t N, uint32_t n_theta,
                      float *out, void *hip_stream);
 
