@@ -150,6 +150,87 @@ static void mlp_binary32(const orc_model *m, const double *theta, const double *
     a[1] = x[1];
 }
 
+/* Mode 4 of orc_rollout: the whole step at binary32, i.e. the oracle's own formulas below
+ * (features, controller, rate limit, control map, kinematic model) evaluated in C float arithmetic
+ * with the math library's float functions, so that every operation, not only the stored values,
+ * carries a binary32 rounding error. Like mode 3 it reproduces no particular float implementation;
+ * it gives the closed loop perturbations of the size a binary32 implementation makes. */
+static float wrap_f(float a)
+{
+    const float pi = (float)ORC_PI, two_pi = (float)(2.0 * ORC_PI);
+    if (a >= pi) a -= two_pi;
+    else if (a < -pi) a += two_pi;
+    return a;
+}
+
+static void step_binary32(const orc_model *m, const double *theta, const float z[4],
+                          const float goal[4], float d_near, const float a_prev[2], float a[2],
+                          float zn[4])
+{
+    /* features, eq. (3) */
+    float s[ORC_MAX_WIDTH];
+    const float c = cosf(z[2]), sn = sinf(z[2]);
+    const float gx = goal[0] - z[0], gy = goal[1] - z[1];
+    const float xi_g = c * gx + sn * gy, eta_g = -sn * gx + c * gy;
+    const float dphi = wrap_f(goal[2] - z[2]);
+    const float dcap = (float)m->d_cap, dn = d_near < dcap ? d_near : dcap;
+    if (m->feature_set == ORC_FEAT_PAPER) {
+        s[0] = xi_g / (float)m->norm_xi;
+        s[1] = eta_g / (float)m->norm_eta;
+        s[2] = dphi / (float)m->norm_phi;
+        s[3] = (goal[3] - z[3]) / (float)m->norm_v;
+        s[4] = a_prev[0];
+    } else {
+        s[0] = xi_g / (float)m->norm_xi;
+        s[1] = eta_g / (float)m->norm_eta;
+        s[2] = dphi / (float)m->norm_phi;
+        s[3] = z[3] / (float)m->norm_v;
+        s[4] = dn / dcap;
+        s[5] = a_prev[0];
+        if (m->feature_set == ORC_FEAT_EIGHT) {
+            s[6] = (goal[3] - z[3]) / (float)m->norm_v;
+            s[7] = a_prev[1];
+        }
+    }
+    /* controller, eq. (4) */
+    float x[ORC_MAX_WIDTH], y[ORC_MAX_WIDTH];
+    for (int i = 0; i < m->widths[0]; ++i) x[i] = s[i];
+    const double *p = theta;
+    for (int l = 0; l < m->n_layers; ++l) {
+        const int nin = m->widths[l], nout = m->widths[l + 1];
+        const double *W = p, *b = p + (size_t)nout * nin;
+        for (int o = 0; o < nout; ++o) {
+            float acc = (float)b[o];
+            for (int i = 0; i < nin; ++i) acc += (float)W[(size_t)o * nin + i] * x[i];
+            y[o] = tanhf(acc);
+        }
+        for (int o = 0; o < nout; ++o) x[o] = y[o];
+        p += (size_t)nout * nin + nout;
+    }
+    a[0] = x[0];
+    a[1] = x[1];
+    /* rate limit, control map and model, Sect. II-F */
+    if (m->delta_rate_max > 0.0) {
+        const float r = (float)m->delta_rate_max * (float)m->dt / (float)m->delta_max;
+        if (a[0] < a_prev[0] - r) a[0] = a_prev[0] - r;
+        if (a[0] > a_prev[0] + r) a[0] = a_prev[0] + r;
+    }
+    const float delta = (float)m->delta_max * a[0];
+    const float u = (float)m->u_min + (a[1] + 1.0f) / 2.0f * ((float)m->u_max - (float)m->u_min);
+    const float L = (float)m->lf + (float)m->lr, dt = (float)m->dt;
+    const float beta = atanf((float)m->lr * tanf(delta) / L);
+    const float xd = z[3] * cosf(z[2] + beta) / cosf(beta);
+    const float yd = z[3] * sinf(z[2] + beta) / cosf(beta);
+    const float phid = z[3] * tanf(delta) / L;
+    zn[0] = z[0] + dt * xd;
+    zn[1] = z[1] + dt * yd;
+    zn[2] = wrap_f(z[2] + dt * phid);
+    float vn = z[3] + dt * u;
+    if (vn < (float)m->v_min) vn = (float)m->v_min;
+    if (vn > (float)m->v_max) vn = (float)m->v_max;
+    zn[3] = vn;
+}
+
 /* Heading angles are kept in [-pi, pi). Every difference wrapped here is within one turn of
  * that range, so a single correction suffices. */
 double orc_wrap_angle(double a)
@@ -309,7 +390,9 @@ static int goal_reached(const orc_model *m, const double z[4], const double goal
 /* +inf on any collision. Two optional terms (weights 0 by default) add the terminal heading and */
 /* speed errors to the goal setpoint, for missions whose setpoints prescribe them (Sect. III).   */
 /* fp32_state = 1 rounds the state to float after every step; 2 also rounds the features and the */
-/* applied controls; 3 in addition evaluates the controller at binary32 precision (mlp_binary32). */
+/* applied controls; 3 in addition evaluates the controller at binary32 precision (mlp_binary32); */
+/* 4 computes the nearest distance and the whole step at binary32 (step_binary32), the effort and */
+/* the terminal distance in float as well (collision tests stay binary64 at the float states).   */
 /* The tests use the gap to the plain run to recognise samples whose outcome is ill-conditioned  */
 /* at float precision.                                                                           */
 /* ------------------------------------------------------------------------------------------ */
@@ -321,16 +404,26 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
     ap[0] = sc->a_prev[0];
     ap[1] = sc->a_prev[1];
     double effort = 0.0;
+    float effort_f = 0.0f;
     int collided = 0, first = -1;
     double min_margin = INFINITY, min_abs_face = INFINITY;
     for (int h = 0; h <= sc->T; ++h) {
         double t = (double)h * m->dt;
         double pose[3] = { z[0], z[1], z[2] };
         double d2min = INFINITY;
+        float d2min_f = INFINITY;
         int hit = 0;
         for (int j = 0; j < sc->P; ++j) {
             double p[2];
             orc_extrapolate(sc->points + 4 * (size_t)j, t, p);
+            if (fp32_state == 4) {
+                const double *q = sc->points + 4 * (size_t)j;
+                const float tf = (float)h * (float)m->dt;
+                const float dxf = ((float)q[0] + tf * (float)q[2]) - (float)z[0];
+                const float dyf = ((float)q[1] + tf * (float)q[3]) - (float)z[1];
+                const float d2f = dxf * dxf + dyf * dyf;
+                if (d2f < d2min_f) d2min_f = d2f;
+            }
             if (orc_point_inside(m, pose, p)) hit = 1;
             double mg = orc_margin(m, pose, p);
             if (mg < min_margin) min_margin = mg;
@@ -353,6 +446,23 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
         }
         if (h == sc->T) break;
 
+        if (fp32_state == 4) {
+            float zf[4], gf[4], apf[2] = { (float)ap[0], (float)ap[1] }, af[2], znf[4];
+            for (int q = 0; q < 4; ++q) {
+                zf[q] = (float)z[q];
+                gf[q] = (float)sc->goal[q];
+            }
+            step_binary32(m, theta, zf, gf, sqrtf(d2min_f), apf, af, znf);
+            effort_f += af[0] * af[0] + af[1] * af[1];
+            if (rec->controls) {
+                rec->controls[2 * (size_t)h] = af[0];
+                rec->controls[2 * (size_t)h + 1] = af[1];
+            }
+            for (int q = 0; q < 4; ++q) z[q] = znf[q];
+            ap[0] = af[0];
+            ap[1] = af[1];
+            continue;
+        }
         double s[ORC_MAX_WIDTH], a_raw[2], a[2], delta, u, zn[4];
         orc_features(m, z, sc->goal, d_near, ap, s);
         if (fp32_state >= 2)
@@ -377,6 +487,11 @@ void orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta, i
     }
     double gx = z[0] - sc->goal[0], gy = z[1] - sc->goal[1];
     double cost = sqrt(gx * gx + gy * gy) + m->effort_weight * m->dt * effort;
+    if (fp32_state == 4) {
+        const float gxf = (float)z[0] - (float)sc->goal[0], gyf = (float)z[1] - (float)sc->goal[1];
+        cost = sqrtf(gxf * gxf + gyf * gyf) +
+               (float)m->effort_weight * (float)m->dt * effort_f;
+    }
     cost += m->goal_heading_weight * fabs(orc_wrap_angle(sc->goal[2] - z[2]));
     cost += m->goal_speed_weight * fabs(sc->goal[3] - z[3]);
     if (collided || isnan(cost)) cost = INFINITY;

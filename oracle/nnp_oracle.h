@@ -91,6 +91,9 @@ int    orc_point_inside(const orc_model *m, const double pose[3], const double p
 double orc_face_distance(const orc_model *m, const double pose[3], const double p[2]);
 double orc_margin(const orc_model *m, const double pose[3], const double p[2]);
 
+/* fp32_state: 0 binary64 throughout; 1..4 inject binary32 rounding (1: state after every step,
+ * 2: also features and applied controls, 3: also the controller, 4: the whole step computed in
+ * binary32), used by the tests to recognise samples whose outcome is ill-conditioned. */
 void   orc_rollout(const orc_model *m, const orc_scene *sc, const double *theta,
                    int fp32_state, orc_record *rec);
 void   orc_rollout_samples(const orc_model *m, const orc_scene *sc, uint64_t seed, uint32_t inst,

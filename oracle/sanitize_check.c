@@ -147,7 +147,7 @@ static void run_case(const orc_model *m, int P, int moving, int blocked, int T, 
     double *dn = (double *)malloc(sizeof(double) * M * (size_t)(T + 1));
     double c[5], mm[5], mf[5];
     int col[5], first[5];
-    for (int mode = 0; mode <= 3; ++mode) {
+    for (int mode = 0; mode <= 4; ++mode) {
         orc_rollout_samples(m, &sc, 7u, 3u, idx, M, mode, tr, co, dn, c, col, first, mm, mf);
         if (mode == 0) CHECK(c[2] == cost[best] || (isinf(c[2]) && isinf(cost[best])));
     }

@@ -3,12 +3,20 @@
 The GPU computes in binary32, the oracle in binary64, and the closed loop feeds rounding back
 through the controller, so the comparison is made sample by sample as follows.
 
-1. Conditioning. The oracle also runs each sample twice more with float rounding injected: the
-   state rounded after every step, and in addition the features and the applied controls. A
-   sample is well conditioned when both runs stay within a twentieth of the tolerances below of the
-   binary64 run; closed-loop trajectories and costs are compared only for well-conditioned
-   samples (the excluded count is reported and bounded by the caller). Every sample, well
-   conditioned or not, goes through the step-by-step check 2b and the flag check 3.
+1. Conditioning. Besides the binary64 run, the oracle runs every sample four more times with
+   binary32 rounding: the state rounded after every step (mode 1), in addition the features and
+   the applied controls (mode 2), in addition the controller itself, every partial sum and tanh
+   rounded (mode 3), and the whole step computed in binary32 arithmetic (mode 4: nearest
+   distance, features, controller, control map, model, effort), which makes rounding errors of
+   the size a binary32 implementation makes in every operation. A sample is ill-conditioned when
+   any of these runs leaves half the tolerances of rules 2 and 4 (trajectory 5e-5, cost 5e-6);
+   its closed-loop trajectory and cost are then not compared (the count is reported and bounded
+   by the caller). Half, not the whole tolerance: the GPU's run is one more binary32 realisation
+   of the same chaotic closed loop; over 1509 C1 and paper-preset samples its deviation from
+   binary64 was up to 1.4x the largest of the four at the 90th percentile (3.4x at the 99th), and
+   at the whole tolerance a few samples per thousand whose oracle runs stayed inside it left it
+   on the GPU. Every sample, well conditioned or not, goes through the step-by-step check 2b and
+   the flag check 3.
 2. Trajectories (up to the oracle's first collision step): per component
    |gpu - ref| <= 1e-4 * max(|ref|, 1) (x, y in m, v in m/s); headings are compared modulo
    2 pi with an absolute 1e-4 rad.
@@ -40,6 +48,8 @@ CTRL_STEP_ATOL = 2e-5
 MODEL_STEP_RTOL = 1e-6
 COST_RTOL = 1e-5
 FACE_EPS = 1e-5
+COND_FRACTION = 0.5           # rule 1: a rounded oracle run must stay within this share of the
+COND_MODES = (1, 2, 3, 4)     # tolerances; the oracle's binary32 rounding modes used
 TWO_PI = 2.0 * math.pi
 
 
@@ -69,10 +79,10 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
     if theta_rows is None:
         ref = oracle.rollout_samples(m, ob, seed, inst, idx)
         perturbed = [oracle.rollout_samples(m, ob, seed, inst, idx, fp32_state=mode)
-                     for mode in (1, 2)]
+                     for mode in COND_MODES]
     else:
         ref = _rollout_rows(m, ob, theta_rows, 0)
-        perturbed = [_rollout_rows(m, ob, theta_rows, mode) for mode in (1, 2)]
+        perturbed = [_rollout_rows(m, ob, theta_rows, mode) for mode in COND_MODES]
     g_traj = gpu["traj"][idx].astype(np.float64)
     g_ctrl = gpu["controls"][idx].astype(np.float64)
     g_cost = gpu["cost"][idx].astype(np.float64)
@@ -128,13 +138,15 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
             if math.isinf(c64) != math.isinf(c32):
                 cbad = True
             else:
-                cbad = (not math.isinf(c64)) and abs(c32 - c64) > 0.05 * COST_RTOL * max(c64, 1.0)
-            ok = ok and e32 <= 0.05 * TRAJ_RTOL and not cbad
+                cbad = ((not math.isinf(c64)) and
+                        abs(c32 - c64) > COND_FRACTION * COST_RTOL * max(c64, 1.0))
+            ok = ok and e32 <= COND_FRACTION * TRAJ_RTOL and not cbad
         well[r] = ok
         n_ill += not well[r]
 
     # 2. trajectories and controls, 4. costs
     bad_traj, bad_cost, face_sensitive, max_traj, max_cost = [], [], 0, 0.0, 0.0
+    finite_compared = 0
     for r in np.flatnonzero(well):
         upto = (first64[r] if first64[r] >= 0 else T) + 1
         e = _traj_err(g_traj[r, :upto], ref["traj"][r, :upto])
@@ -154,11 +166,13 @@ def check_samples(preset, scene, gpu: dict, idx, seed: int, inst: int = 0,
             continue
         rel = abs(cg - c64) / max(c64, 1.0)
         max_cost = max(max_cost, rel)
+        finite_compared += 1
         if rel > COST_RTOL:
             bad_cost.append((int(idx[r]), cg, c64))
     assert not bad_traj, f"trajectory mismatch (sample, err, step): {bad_traj[:10]}"
     assert not bad_cost, f"cost mismatch (sample, gpu, oracle): {bad_cost[:10]}"
-    return dict(n=len(idx), ill_conditioned=n_ill, undecided=undecided,
+    return dict(n=len(idx), ill_conditioned=n_ill, finite=int(np.isfinite(ref["cost"]).sum()),
+                finite_compared=finite_compared, undecided=undecided,
                 face_sensitive=face_sensitive, collided=int((first64 >= 0).sum()),
                 max_step_ctrl_err=max_ctrl, max_step_model_err=max_model,
                 max_traj_err=max_traj, max_cost_err=max_cost)

@@ -21,6 +21,18 @@ if not torch.cuda.is_available():
 
 from paper_1904_06680_amd.nnplan import NNP_EINVAL, NNP_INFEASIBLE, NnpError, Planner  # noqa: E402
 
+# Largest share of ill-conditioned samples (parity rule 1) accepted per case: the measured share
+# on these seeded inputs plus a small margin. Measured: C0 0 of 1024 (every scene); C1 scene 4 at
+# N = 768: 33 and 35 (4.3%, 4.6%); the offset rectangle 26 of 512 (5.1%); C1 at full size 39 of
+# 320 checked samples on scene 4 (12%: the set is weighted towards collision-free samples, which
+# run all 50 steps) and 2 of 254 on scene 1; edge sizes 0; the paper preset (100 steps,
+# steering-rate clip, the tiny Table III networks) 85, 140 and 120 of 512 (17-27%); the goal-state
+# cost terms 0 (C0) and 50 of 768 (6.5%, paper preset at T = 60). Collided samples are compared
+# only up to their first collision, so the share is highest among collision-free ones.
+ILL_BOUND = dict(c0=0.01, c1_reduced=0.06, c1_full=0.15, c1_offset=0.07, edge=0.02,
+                 paper={(5, 2, 2): 0.2, (5, 10, 2): 0.3, (5, 10, 10, 2): 0.27},
+                 goal_c0=0.01, goal_paper=0.09)
+
 
 def say(*a):
     print(*a, flush=True)
@@ -76,8 +88,9 @@ def test_c0_rollout_and_plan_parity(c0_planner, seed):
     say(f"C0 parity: scene {seed}, N={N}, T={sc.T}, P={sc.P}")
     g = np_out(c0_planner.rollout(sc, N, seed=seed))
     st = check_samples(scenes.C0, sc, g, np.arange(N), seed)
-    assert st["ill_conditioned"] <= 0.01 * N, st
     say("  ", st)
+    assert st["ill_conditioned"] <= ILL_BOUND["c0"] * N, st
+    assert st["finite_compared"] >= st["finite"] - ILL_BOUND["c0"] * N, st
     out = c0_planner.plan(sc, N, seed=seed)
     best = int(out["best_index"].item())
     m, ob = oracle_scene(scenes.C0, sc)
@@ -93,15 +106,19 @@ def test_c0_rollout_and_plan_parity(c0_planner, seed):
                           oracle.theta(seed, 0, best, 1, 146)[0])
 
 
-@pytest.mark.parametrize("seed", [0, 4])
+@pytest.mark.parametrize("seed", [4, 1])
 def test_c1_reduced_n_parity(c1_planner, seed):
-    sc = scenes.scene_c1(seed)
+    """Every sample of a C1 scene with the full 3000-point layout at N = 768. Scene 4 is the C1
+    scene with the most collision-free samples (about one in eight), so the cost rule compares
+    finite costs; most other C1 scenes have none at this N."""
+    sc = scenes.scene_c1(4)
     N = 768
-    say(f"C1 parity: scene {seed}, N={N}, T={sc.T}, P={sc.P}")
+    say(f"C1 parity: scene 4, seed {seed}, N={N}, T={sc.T}, P={sc.P}")
     g = np_out(c1_planner.rollout(sc, N, seed=seed))
     st = check_samples(scenes.C1, sc, g, np.arange(N), seed)
     say("  ", st)
-    assert st["ill_conditioned"] <= 0.2 * N, st
+    assert st["ill_conditioned"] <= ILL_BOUND["c1_reduced"] * N, st
+    assert st["finite_compared"] >= 60, st
 
 
 def test_c1_offset_rectangle_parity():
@@ -122,35 +139,48 @@ def test_c1_offset_rectangle_parity():
             assert np.array_equal(o[k], outs[0][k]), k
     st = check_samples(preset, sc, outs[1], np.arange(N), 11)
     say("  ", st)
-    assert st["ill_conditioned"] <= 0.2 * N, st
+    assert st["ill_conditioned"] <= ILL_BOUND["c1_offset"] * N, st
+    assert st["finite_compared"] >= 30, st
 
 
-def test_c1_full_size_sampled(c1_planner):
-    """N = 65536, T = 50, P = 3000 in the benchmark's launch configuration: 192 random samples
-    and the 64 lowest GPU costs are recomputed by the oracle; the plan's argmin, cost and
-    trajectory are checked against the rollout of the same samples."""
-    sc = scenes.scene_c1(0)
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("scene_id", [4, 1])
+def test_c1_full_size_sampled(c1_planner, scene_id):
+    """N = 65536, T = 50, P = 3000 in the benchmark's launch configuration, on the C1 scenes
+    with the most (4: 8310) and a few (1: 126) collision-free samples. The oracle computes the
+    cost of every sample, so the plan's index is checked against the oracle's argmin over all of
+    them (rule 5, exact or tie band); the 64 lowest GPU costs, up to 128 further finite ones and
+    128 random samples are checked in full (trajectories, controls, flags, costs)."""
+    sc = scenes.scene_c1(scene_id)
     N, seed = 65536, 0
-    say(f"C1 full size: scene 0, N={N}, T={sc.T}, P={sc.P}")
+    say(f"C1 full size: scene {scene_id}, N={N}, T={sc.T}, P={sc.P}")
     g = np_out(c1_planner.rollout(sc, N, seed=seed))
-    rng = np.random.default_rng(0)
-    top = np.argsort(g["cost"], kind="stable")[:64]
-    idx = np.unique(np.concatenate([rng.choice(N, 192, replace=False), top]))
-    st = check_samples(scenes.C1, sc, g, idx, seed)
-    say("  ", st)
-    assert st["ill_conditioned"] <= 0.2 * len(idx), st
     out = c1_planner.plan(sc, N, seed=seed)
     best = int(out["best_index"].item())
     gc = g["cost"]
     assert best == int(np.flatnonzero(gc == gc.min())[0])
     assert np.array_equal(out["traj"].cpu().numpy(), g["traj"][best])
-    # argmin among the oracle-checked candidates (the true best is among the GPU's 64 lowest
-    # whenever the costs agree within tolerance)
+    assert np.array_equal(out["controls"].cpu().numpy(), g["controls"][best])
     m, ob = oracle_scene(scenes.C1, sc)
-    ref = oracle.rollout_samples(m, ob, seed, 0, top, want_traj=False, want_controls=False)
-    cand = np.full(N, math.inf)
-    cand[top] = ref["cost"]
-    say("  argmin:", check_argmin(cand, best))
+    say("   oracle costs of all samples ...")
+    ref = oracle.rollout_samples(m, ob, seed, 0, np.arange(N), want_traj=False,
+                                 want_controls=False)
+    kind = check_argmin(ref["cost"], best)
+    say("   argmin:", kind, "gpu", best, float(gc[best]), "oracle", int(np.argmin(ref["cost"])),
+        float(np.min(ref["cost"])), "finite (oracle, gpu):", int(np.isfinite(ref["cost"]).sum()),
+        int(np.isfinite(gc).sum()))
+    assert kind in ("exact", "tie-band")
+    assert abs(float(out["cost"].item()) - ref["cost"][best]) <= 1e-5 * max(ref["cost"][best], 1.0)
+    rng = np.random.default_rng(scene_id)
+    order = np.argsort(gc, kind="stable")
+    fin = order[np.isfinite(gc[order])]
+    more = fin[64:]
+    more = rng.choice(more, min(128, len(more)), replace=False) if len(more) else more
+    idx = np.unique(np.concatenate([order[:64], more, rng.choice(N, 128, replace=False)]))
+    st = check_samples(scenes.C1, sc, g, idx, seed)
+    say("  ", st)
+    assert st["ill_conditioned"] <= ILL_BOUND["c1_full"] * len(idx), st
+    assert st["finite_compared"] >= min(100, int(0.8 * min(len(fin), 192))), st
 
 
 def test_k_layouts_bit_identical():
@@ -220,6 +250,7 @@ def test_edge_sizes_parity(c1_planner, P, N, T):
     g = np_out(c1_planner.rollout(sc, N, seed=P + N))
     st = check_samples(scenes.C1, sc, g, np.arange(N), P + N)
     say("  ", st)
+    assert st["ill_conditioned"] <= max(1, ILL_BOUND["edge"] * N), st
     out = c1_planner.plan(sc, N, seed=P + N)
     best = int(out["best_index"].item())
     gc = g["cost"]
@@ -281,7 +312,8 @@ def test_paper_preset_parity(widths):
     g = np_out(pl.rollout(sc, N, seed=11))
     st = check_samples(preset, sc, g, np.arange(N), 11)
     say("  ", st)
-    assert st["ill_conditioned"] <= 0.5 * N, st
+    assert st["ill_conditioned"] <= ILL_BOUND["paper"][widths] * N, st
+    assert st["finite_compared"] >= 0.35 * st["finite"], st     # measured 0.41-0.59
     # the steering-rate limit holds on every GPU trajectory
     a0 = g["controls"][:, :, 0]
     assert np.all(np.abs(np.diff(a0, axis=1)) <= 0.05 + 1e-6)
@@ -302,7 +334,7 @@ def test_goal_heading_and_speed_cost_terms_parity(preset_name):
     g = np_out(pl.rollout(sc, N, seed=21))
     st = check_samples(preset, sc, g, np.arange(N), 21)
     say("  ", st)
-    assert st["ill_conditioned"] <= (0.05 if preset_name == "c0" else 0.5) * N, st
+    assert st["ill_conditioned"] <= ILL_BOUND["goal_" + preset_name] * N, st
     out = pl.plan(sc, N, seed=21)
     gc = g["cost"]
     assert int(out["best_index"].item()) == int(np.flatnonzero(gc == gc.min())[0])

@@ -743,6 +743,122 @@ def _numpy_rollout(preset, sc, th, fp32_state):
     return dict(traj=traj, controls=ctrl, cost=cost, first_collision=first)
 
 
+def _numpy_rollout_binary32(preset, sc, th):
+    """The oracle's rounding mode 4 written from its definition with numpy float32 arrays: the
+    nearest distance, features, controller (sums in index order), rate limit, control map and
+    model step, the effort and the terminal distance all in binary32 arithmetic; collision tests
+    in binary64 at the binary32 states."""
+    F = np.float32
+    w = list(preset["widths"])
+    N = len(th)
+    dt, lf, lr = F(preset["dt"]), F(preset["lf"]), F(preset["lr"])
+    L = F(lf + lr)
+    pi, two_pi = F(math.pi), F(2 * math.pi)
+    wrap = lambda a: np.where(a >= pi, a - two_pi, np.where(a < -pi, a + two_pi, a))  # noqa: E731
+    z = np.tile(sc.z0.astype(F), (N, 1))
+    g = sc.goal.astype(F)
+    ap = np.tile(sc.a_prev_or_idle(preset).astype(F), (N, 1))
+    P = sc.points.astype(np.float64)
+    Pf = sc.points.astype(F)
+    thf = th.astype(F)
+    traj = np.empty((N, sc.T + 1, 4))
+    ctrl = np.empty((N, sc.T, 2))
+    first = np.full(N, -1)
+    E = np.zeros(N, F)
+    rate = (F(preset["delta_rate_max"]) * dt / F(preset["delta_max"])
+            if preset["delta_rate_max"] else None)
+    for h in range(sc.T + 1):
+        traj[:, h] = z
+        zd = z.astype(np.float64)
+        q = P[:, :2] + h * float(dt) * P[:, 2:]
+        dx = q[None, :, 0] - zd[:, None, 0]
+        dy = q[None, :, 1] - zd[:, None, 1]
+        c, s = np.cos(zd[:, 2])[:, None], np.sin(zd[:, 2])[:, None]
+        xi, eta = c * dx + s * dy, -s * dx + c * dy
+        inside = (xi < float(F(preset["front"]))) & (-xi < float(F(preset["rear"]))) & \
+                 (np.abs(eta) < float(F(preset["half_width"])))
+        first = np.where((first < 0) & inside.any(1), h, first)
+        if h == sc.T:
+            break
+        tf = F(F(h) * dt)
+        dxf = (Pf[None, :, 0] + tf * Pf[None, :, 2]) - z[:, None, 0]
+        dyf = (Pf[None, :, 1] + tf * Pf[None, :, 3]) - z[:, None, 1]
+        dn = np.sqrt((dxf * dxf + dyf * dyf).min(1)) if len(P) else np.full(N, np.inf, F)
+        gx, gy = g[0] - z[:, 0], g[1] - z[:, 1]
+        cc, ss = np.cos(z[:, 2]), np.sin(z[:, 2])
+        e = wrap(g[2] - z[:, 2])
+        xg, yg = (cc * gx + ss * gy) / F(preset["norm_xi"]), (-ss * gx + cc * gy) / F(preset["norm_eta"])
+        if preset["feature_set"] == scenes.FEAT_PAPER:
+            feats = [xg, yg, e / F(preset["norm_phi"]), (g[3] - z[:, 3]) / F(preset["norm_v"]), ap[:, 0]]
+        else:
+            dc = F(preset["d_cap"])
+            feats = [xg, yg, e / F(preset["norm_phi"]), z[:, 3] / F(preset["norm_v"]),
+                     np.minimum(dn, dc) / dc, ap[:, 0]]
+            if preset["feature_set"] == scenes.FEAT_EIGHT:
+                feats += [(g[3] - z[:, 3]) / F(preset["norm_v"]), ap[:, 1]]
+        x = np.stack(feats, 1).astype(F)
+        off = 0
+        for l in range(len(w) - 1):
+            W = thf[:, off:off + w[l + 1] * w[l]].reshape(N, w[l + 1], w[l])
+            off += w[l + 1] * w[l]
+            acc = thf[:, off:off + w[l + 1]].copy()
+            off += w[l + 1]
+            for i in range(w[l]):
+                acc = acc + W[:, :, i] * x[:, i:i + 1]
+            x = np.tanh(acc)
+        a = x.copy()
+        if rate is not None:
+            a[:, 0] = np.minimum(np.maximum(a[:, 0], ap[:, 0] - rate), ap[:, 0] + rate)
+        ctrl[:, h] = a
+        delta = F(preset["delta_max"]) * a[:, 0]
+        u = F(preset["u_min"]) + (a[:, 1] + F(1)) / F(2) * (F(preset["u_max"]) - F(preset["u_min"]))
+        beta = np.arctan(lr * np.tan(delta) / L)
+        v = z[:, 3]
+        nz = np.empty_like(z)
+        nz[:, 0] = z[:, 0] + dt * (v * np.cos(z[:, 2] + beta) / np.cos(beta))
+        nz[:, 1] = z[:, 1] + dt * (v * np.sin(z[:, 2] + beta) / np.cos(beta))
+        nz[:, 2] = wrap(z[:, 2] + dt * (v * np.tan(delta) / L))
+        nz[:, 3] = np.minimum(np.maximum(v + dt * u, F(preset["v_min"])), F(preset["v_max"]))
+        E = E + (a[:, 0] * a[:, 0] + a[:, 1] * a[:, 1])
+        z = nz
+        ap = a
+    cost = (np.sqrt((z[:, 0] - g[0]) ** 2 + (z[:, 1] - g[1]) ** 2) +
+            F(preset["effort_weight"]) * dt * E).astype(np.float64)
+    cost[first >= 0] = np.inf
+    return dict(traj=traj, controls=ctrl, cost=cost, first_collision=first)
+
+
+@pytest.mark.parametrize("case", [0, 1, 2, 3], ids=["c0", "c1", "paper", "moving"])
+def test_binary32_mode_matches_numpy_definition(case):
+    """Rounding mode 4 (the whole step in binary32) against the numpy float32 rollout written from
+    its definition. The two use different float sin/cos/tan/atan/tanh (glibc's and numpy's, each
+    within a few ulp), so they agree to float-rounding size carried through the closed loop, not
+    bit for bit (measured over these eight steps: states 4e-6 relative, controls 3.4e-5 on the
+    8-32-32-2 network, whose gain is largest), while a dropped term, a wrong sign or a skipped
+    wrap moves them by 1e-2 or more. Every state and control of mode 4 is a binary32 value, and
+    mode 4 differs from the binary64 run by float-rounding amounts."""
+    name, preset, sc, _ = _pin_cases()[case]
+    sc = scenes.Scene(sc.z0, sc.goal, sc.points, min(sc.T, 8))
+    m = oracle.make_model(preset)
+    ob = oracle.SceneBuf(sc.z0, sc.goal, sc.a_prev_or_idle(preset), sc.points, sc.T)
+    N, seed = 24, 4
+    th = oracle.theta(seed, 0, 0, N, oracle.n_theta(m))
+    got = oracle.rollout_samples(m, ob, seed, 0, np.arange(N), fp32_state=4)
+    want = _numpy_rollout_binary32(preset, sc, th)
+    ref = oracle.rollout_samples(m, ob, seed, 0, np.arange(N))
+    assert np.array_equal(got["first_collision"], want["first_collision"]), name
+    scale = np.maximum(np.abs(want["traj"]), 1.0)
+    assert np.all(np.abs(got["traj"] - want["traj"]) <= 1e-4 * scale), name
+    assert np.all(np.abs(got["controls"] - want["controls"]) <= 1e-3), name
+    fin = np.isfinite(want["cost"])
+    assert np.array_equal(fin, np.isfinite(got["cost"]))
+    assert np.all(np.abs(got["cost"][fin] - want["cost"][fin]) <= 1e-4 * np.maximum(want["cost"][fin], 1))
+    assert np.array_equal(_f32(got["traj"]), got["traj"])
+    assert np.array_equal(_f32(got["controls"]), got["controls"])
+    d = np.abs(got["traj"] - ref["traj"]).max()
+    assert 1e-9 < d < 1e-3, (name, d)
+
+
 @pytest.mark.parametrize("case", [0, 1, 2, 3], ids=["c0", "c1", "paper", "moving"])
 def test_rounding_modes_match_numpy_definition(case):
     """The oracle's float-rounding modes (used by the parity tests to measure how sensitive each
