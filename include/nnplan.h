@@ -42,6 +42,7 @@ extern "C" {
 #define NNP_MAX_T 4096        /* longest horizon accepted                                    */
 #define NNP_MAX_P (1 << 22)   /* most obstacle points accepted                               */
 #define NNP_MAX_BATCH 65535   /* most problems in one nnp_plan_batch call                    */
+#define NNP_NOALLOC_SCRATCH_BYTES (4 << 20) /* device scratch of nnp_plan_noalloc, per GPU      */
 
 /* Feature vectors of eq. (3) (Sect. II-E) and the two extended variants:
  * NNP_FEAT_PAPER  5 inputs: [xi_g/dxi, eta_g/deta, wrap(phi_g-phi)/dphi, (v_g-v)/dv, a_prev[0]]
@@ -157,6 +158,21 @@ int nnp_set_record_limit(nnp_handle *h, uint64_t bytes);
  * and names the buffer in nnp_last_error. Lowering the cap frees nothing already allocated.
  * Returns NNP_EINVAL for h == NULL. */
 int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes);
+
+/* nnp_plan for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): same arguments, same validation and the same
+ * outputs bit for bit as nnp_plan, but the call allocates nothing, on the device or the host. Its
+ * argmin key and extrapolation table live in a fixed file-scope device array of
+ * NNP_NOALLOC_SCRATCH_BYTES (4 MiB) that every GPU the library runs on holds until the process
+ * ends; the winner's outputs are re-simulated (no per-sample records). Limit: the table of
+ * (T + 1) * (P rounded up to a multiple of 64) / 2 point pairs of 16 bytes, plus 64 pairs of
+ * slack and 256 bytes for the key, must fit (T = 50 allows P up to 10240); larger problems
+ * return NNP_EINVAL with the sizes in nnp_last_error. The key is reset by the call itself. All
+ * calls on one GPU share that GPU's array: calls that overlap on one GPU (on different streams,
+ * from different threads or handles) race and must be serialised by the caller; consecutive
+ * calls on one stream are ordered. The handle's timing instrumentation does not record these
+ * calls. Returns the codes of nnp_plan. */
+int nnp_plan_noalloc(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
 
 /* Many independent problems in one call: the same plan as nnp_plan for every probs[i] (each with
  * its own N, T, P, obstacles, seed and warm start), written to results[i]. All problems are

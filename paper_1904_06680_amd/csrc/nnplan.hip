@@ -18,9 +18,11 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -628,6 +630,37 @@ const Variant *find_variant(const nnp_model *m, int K)
 
 thread_local std::string g_create_error;
 
+// Allocation-free planning (nnp_plan_noalloc): the argmin key (first 256 bytes) and the
+// extrapolation table live in one file-scope device array. Each GPU holds its own copy at its own
+// address, resolved once per device with hipGetSymbolAddress while that device is current; host
+// code uses only that address (the array's name is a host-side stand-in, not a device pointer).
+constexpr size_t NOALLOC_KEY_BYTES = 256;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NNP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of the current device's copy of `scratch` (the caller has made `device`
+// current).
+hipError_t scratch_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
 bool finite_f(float v) { return isfinite(v); }
 
 }  // namespace
@@ -654,6 +687,7 @@ struct nnp_handle {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     double acc_ms = 0.0;
     int64_t launches = 0;
+    void *scratch = nullptr;           // this device's copy of the file-scope scratch array
     std::string err;
 };
 
@@ -666,9 +700,30 @@ int fail(nnp_handle *h, int code, const std::string &msg)
     return code;
 }
 
+// Fixed messages: copied into the handle's error string (capacity reserved by nnp_create, so
+// validation allocates no host memory).
+int fail(nnp_handle *h, int code, const char *msg)
+{
+    if (h) h->err.assign(msg);
+    else g_create_error = msg;
+    return code;
+}
+
 int hip_fail(nnp_handle *h, hipError_t e, const char *what)
 {
     return fail(h, NNP_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Error paths of the allocation-free entry point: the message is copied into the handle's error
+// string, whose capacity nnp_create reserves, so that no host memory is allocated either.
+int fail_fixed(nnp_handle *h, int code, const char *msg, const char *detail = nullptr)
+{
+    h->err.assign(msg);
+    if (detail) {
+        h->err.append(": ");
+        h->err.append(detail);
+    }
+    return code;
 }
 
 int check_model(const nnp_model *m, std::string &why)
@@ -921,6 +976,12 @@ int nnp_create(nnp_handle **out, const nnp_model *m, int device)
     h->dm = derive(m);
     h->var = find_variant(m, m->lanes_per_sample);
     h->device = device;
+    h->err.reserve(1024);
+    e = scratch_address(device, &h->scratch);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(nullptr, e, "hipGetSymbolAddress of the scratch array");
+    }
     e = hipMalloc(&h->d_key, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete h;
@@ -996,6 +1057,61 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
     else h->var->launch_replay(a, o, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, record ? "gather_kernel launch" : "replay_kernel launch");
+    h->err.clear();
+    return NNP_OK;
+}
+
+int nnp_plan_noalloc(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream)
+{
+    if (!h) return NNP_EINVAL;
+    if (!r) return fail(h, NNP_EINVAL, "null result");
+    RolloutArgs a;
+    int rc = fill_args(h, p, a);
+    if (rc) return rc;
+    const size_t need = NOALLOC_KEY_BYTES + table_entries(a) * sizeof(float4);
+    if (need > (size_t)NNP_NOALLOC_SCRATCH_BYTES) {
+        char msg[256];
+        snprintf(msg, sizeof msg,
+                 "the extrapolation table of T = %d steps and P = %d points needs %zu bytes of "
+                 "scratch, more than NNP_NOALLOC_SCRATCH_BYTES = %d; use nnp_plan",
+                 p->T, p->P, need, (int)NNP_NOALLOC_SCRATCH_BYTES);
+        return fail_fixed(h, NNP_EINVAL, msg);
+    }
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess) return fail_fixed(h, NNP_EDEVICE, "hipSetDevice", hipGetErrorString(e));
+    if (!h->scratch) {
+        e = scratch_address(h->device, &h->scratch);
+        if (e != hipSuccess)
+            return fail_fixed(h, NNP_EDEVICE, "hipGetSymbolAddress", hipGetErrorString(e));
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *base = static_cast<char *>(h->scratch);
+    unsigned long long *key = reinterpret_cast<unsigned long long *>(base);
+    float4 *ext = reinterpret_cast<float4 *>(base + NOALLOC_KEY_BYTES);
+    a.best_key = key;
+    a.ext = ext;
+    // the table and the key reset (every call starts the argmin from ~0)
+    const long long n = (long long)(p->T + 1) * a.P2;
+    const unsigned tgrid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
+    hipLaunchKernelGGL(extrapolate_kernel, dim3(tgrid), dim3(BLOCK), 0, s,
+                       reinterpret_cast<const float4 *>(p->obst), p->P, a.P2, p->T, h->dm.dt, ext,
+                       key);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail_fixed(h, NNP_EDEVICE, "extrapolate_kernel launch", hipGetErrorString(e));
+    // the rollout without per-sample records, then the winner re-simulated
+    const long long lanes = (long long)a.N * h->var->K;
+    const int rb = rollout_block(h->var->K);
+    h->var->launch_rollout(a, MODE_PLAN, dim3((unsigned)((lanes + rb - 1) / rb)), s);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail_fixed(h, NNP_EDEVICE, "rollout_kernel launch", hipGetErrorString(e));
+    ReplayOut o = {r->theta, r->controls, r->controls_phys, r->traj, r->cost, r->best_index,
+                   r->status, r->goal_reached};
+    h->var->launch_replay(a, o, s);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail_fixed(h, NNP_EDEVICE, "replay_kernel launch", hipGetErrorString(e));
     h->err.clear();
     return NNP_OK;
 }

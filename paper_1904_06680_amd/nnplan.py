@@ -19,7 +19,8 @@ NNP_OK, NNP_INFEASIBLE = 0, 1
 NNP_EINVAL, NNP_ENOMEM, NNP_EDEVICE, NNP_EUNSUPPORTED = -1, -2, -3, -4
 FEAT_PAPER, FEAT_SIX, FEAT_EIGHT = 0, 1, 2
 
-EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_batch", "nnp_rollout",
+EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_noalloc",
+            "nnp_plan_batch", "nnp_rollout",
             "nnp_sample_theta", "nnp_sample_gauss", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
             "nnp_set_record_limit", "nnp_set_workspace_limit", "nnp_version")
 
@@ -85,6 +86,8 @@ def load_library(path: str = LIB):
         "nnp_destroy": (None, [H]),
         "nnp_n_theta": (C.c_int, [H]),
         "nnp_plan": (C.c_int, [H, C.POINTER(nnp_problem), C.POINTER(nnp_result), C.c_void_p]),
+        "nnp_plan_noalloc": (C.c_int, [H, C.POINTER(nnp_problem), C.POINTER(nnp_result),
+                                       C.c_void_p]),
         "nnp_plan_batch": (C.c_int, [H, C.POINTER(nnp_problem), C.c_int, C.POINTER(nnp_result),
                                      C.c_void_p]),
         "nnp_rollout": (C.c_int, [H, C.POINTER(nnp_problem), C.c_void_p,
@@ -126,6 +129,11 @@ def nnp_n_theta(h) -> int:
 
 def nnp_plan(h, problem: nnp_problem, result: nnp_result, stream: int = 0) -> int:
     return load_library().nnp_plan(h, C.byref(problem), C.byref(result), C.c_void_p(stream))
+
+
+def nnp_plan_noalloc(h, problem: nnp_problem, result: nnp_result, stream: int = 0) -> int:
+    return load_library().nnp_plan_noalloc(h, C.byref(problem), C.byref(result),
+                                           C.c_void_p(stream))
 
 
 def nnp_plan_batch(h, problems, results, stream: int = 0) -> int:
@@ -277,13 +285,15 @@ class Planner:
             pr.n_prop = int(n_prop)
         return pr, keep
 
-    def plan_async(self, pr: nnp_problem, out: dict, stream=None):
+    def plan_async(self, pr: nnp_problem, out: dict, stream=None, noalloc: bool = False):
+        """nnp_plan, or nnp_plan_noalloc when noalloc is set, into the tensors of `out`."""
         res = nnp_result()
         for k in ("theta", "controls", "controls_phys", "traj", "cost", "best_index", "status",
                   "goal_reached"):
             t = out.get(k)
             setattr(res, k, t.data_ptr() if t is not None else None)
-        _check(nnp_plan(self.h, pr, res, self._stream() if stream is None else stream), self.h)
+        entry = nnp_plan_noalloc if noalloc else nnp_plan
+        _check(entry(self.h, pr, res, self._stream() if stream is None else stream), self.h)
 
     def alloc_result(self, T: int) -> dict:
         torch, d = self.torch, self._dev()
@@ -297,10 +307,10 @@ class Planner:
                     goal_reached=torch.empty(1, dtype=torch.int32, device=d))
 
     def plan(self, scene, N: int, seed: int = 0, inst: int = 0, warm_theta=None,
-             proposal=None) -> dict:
+             proposal=None, noalloc: bool = False) -> dict:
         pr, keep = self.problem(scene, N, seed, inst, warm_theta=warm_theta, proposal=proposal)
         out = self.alloc_result(scene.T)
-        self.plan_async(pr, out)
+        self.plan_async(pr, out, noalloc=noalloc)
         self.torch.cuda.synchronize(self._dev())
         del keep
         return out
