@@ -37,7 +37,17 @@ typedef struct nnp_fleet_config {
     int32_t warm_start;        /* 1: theta*_{t-1} replaces sample 0 from the second step on    */
     float dt;                  /* sampling time T_s (obstacle motion between steps)           */
     float eps_xi, eps_eta, eps_phi, eps_v; /* waypoint tolerances (Table II)                  */
+    int32_t switch_rule;       /* NNP_SWITCH_STATE or NNP_SWITCH_PLAN (below)                  */
 } nnp_fleet_config;
+
+/* Waypoint switching (Step 4 of Alg. 1, Sect. II-D). NNP_SWITCH_STATE: the next waypoint becomes
+ * the goal setpoint once the vehicle's own state z_{t+1} is within the tolerances.
+ * NNP_SWITCH_PLAN: the recursive logic the goal-setpoint discussion names, based on whether the
+ * last plan reached the setpoint over its horizon: an intermediate waypoint is passed once the
+ * best plan's predicted trajectory comes within the tolerances at any step h = 1..T; the final
+ * waypoint (mission completion, Step 7) still needs the vehicle's own state within them. */
+#define NNP_SWITCH_STATE 0
+#define NNP_SWITCH_PLAN 1
 
 typedef struct nnp_vehicle_spec {
     float z0[4];               /* initial state x, y, phi in [-pi, pi], v                     */

@@ -20,16 +20,19 @@ struct StatusRec {
     float z[4];
     float a[2];
     float cost;
-    int32_t reached;
+    int32_t reached;           // z_{t+1} within the tolerances
     int32_t status;
-    int32_t pad[3];
+    int32_t plan_reached;      // some predicted state z_h, h = 1..T, within the tolerances
+    int32_t pad[2];
 };
 
 struct FleetEps {
     float xi, eta, phi, v;
 };
 
-// z_{t+1} = the plan's first predicted state, a_t = its first control; waypoint check at z_{t+1}.
+// z_{t+1} = the plan's first predicted state, a_t = its first control; waypoint check at z_{t+1}
+// and over the whole predicted trajectory. One vehicle per workgroup of 64 lanes: lane h tests
+// the predicted states h + 1, h + 65, ... (infeasible plans never count as reaching).
 __global__ void fleet_status_kernel(int n, int T, const float *__restrict__ traj,
                                     const float *__restrict__ controls,
                                     const float *__restrict__ cost,
@@ -37,9 +40,21 @@ __global__ void fleet_status_kernel(int n, int T, const float *__restrict__ traj
                                     const float *__restrict__ goals, FleetEps eps,
                                     StatusRec *__restrict__ out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x;
     if (j >= n) return;
-    const float *z = traj + (size_t)j * (T + 1) * 4 + 4;
+    const float *tr = traj + (size_t)j * (T + 1) * 4;
+    const float g[4] = {goals[4 * j], goals[4 * j + 1], goals[4 * j + 2], goals[4 * j + 3]};
+    int any = 0;
+    for (int h = 1 + (int)threadIdx.x; h <= T; h += 64) {
+        const float *z = tr + 4 * (size_t)h;
+        float sn, cs;
+        sincosf(z[2], &sn, &cs);
+        any |= nnp::within_tolerance(eps.xi, eps.eta, eps.phi, eps.v, g, z[0], z[1], z[2], z[3],
+                                     cs, sn);
+    }
+    any = __any(any);
+    if (threadIdx.x != 0) return;
+    const float *z = tr + 4;
     const float *a = controls + (size_t)j * T * 2;
     StatusRec r;
     for (int k = 0; k < 4; ++k) r.z[k] = z[k];
@@ -47,12 +62,12 @@ __global__ void fleet_status_kernel(int n, int T, const float *__restrict__ traj
     r.a[1] = a[1];
     r.cost = cost[j];
     r.status = status[j];
-    const float g[4] = {goals[4 * j], goals[4 * j + 1], goals[4 * j + 2], goals[4 * j + 3]};
     float sn, cs;
     sincosf(r.z[2], &sn, &cs);
     r.reached = nnp::within_tolerance(eps.xi, eps.eta, eps.phi, eps.v, g, r.z[0], r.z[1], r.z[2],
                                       r.z[3], cs, sn);
-    r.pad[0] = r.pad[1] = r.pad[2] = 0;
+    r.plan_reached = any && r.status != NNP_INFEASIBLE;
+    r.pad[0] = r.pad[1] = 0;
     out[j] = r;
 }
 
@@ -137,6 +152,8 @@ int nnp_fleet_create(nnp_fleet **out, nnp_handle *planner, nnp_proposal *proposa
     if (!(c->dt > 0.0f) || !(c->eps_xi >= 0.0f) || !(c->eps_eta >= 0.0f) ||
         !(c->eps_phi >= 0.0f) || !(c->eps_v >= 0.0f))
         return ffail(nullptr, NNP_EINVAL, "dt / tolerances");
+    if (c->switch_rule != NNP_SWITCH_STATE && c->switch_rule != NNP_SWITCH_PLAN)
+        return ffail(nullptr, NNP_EINVAL, "switch_rule must be NNP_SWITCH_STATE or NNP_SWITCH_PLAN");
     nnp_fleet *f = new nnp_fleet();
     f->planner = planner;
     f->prop = c->n_prop > 0 ? proposal : nullptr;
@@ -269,8 +286,8 @@ int nnp_fleet_step(nnp_fleet *f, void *hip_stream, double *latency_ms, int32_t *
                        hipMemcpyHostToDevice, s) != hipSuccess)
         return ffail(f, NNP_EDEVICE, "goal copy failed");
     const FleetEps eps{c.eps_xi, c.eps_eta, c.eps_phi, c.eps_v};
-    hipLaunchKernelGGL(fleet_status_kernel, dim3((na + 63) / 64), dim3(64), 0, s, na, c.T,
-                       f->d_traj, f->d_ctrl, f->d_cost, f->d_status, f->d_goal, eps, f->d_rec);
+    hipLaunchKernelGGL(fleet_status_kernel, dim3(na), dim3(64), 0, s, na, c.T, f->d_traj,
+                       f->d_ctrl, f->d_cost, f->d_status, f->d_goal, eps, f->d_rec);
     if (hipMemcpyAsync(f->h_rec, f->d_rec, (size_t)na * sizeof(StatusRec), hipMemcpyDeviceToHost,
                        s) != hipSuccess)
         return ffail(f, NNP_EDEVICE, "status copy failed");
@@ -289,9 +306,12 @@ int nnp_fleet_step(nnp_fleet *f, void *hip_stream, double *latency_ms, int32_t *
         v.cost = r.cost;
         v.steps += 1;
         if (r.status == NNP_INFEASIBLE) v.infeasible_steps += 1;
-        if (r.reached) {
+        const bool last = v.waypoint + 1 >= (int)(f->wps[(size_t)i].size() / 4);
+        const bool passed = c.switch_rule == NNP_SWITCH_PLAN && !last ? r.plan_reached != 0
+                                                                      : r.reached != 0;
+        if (passed) {
             v.waypoint += 1;
-            if (v.waypoint >= (int)(f->wps[(size_t)i].size() / 4)) v.done = 1;
+            if (last) v.done = 1;
         }
     }
     f->parity ^= 1;

@@ -20,7 +20,10 @@ class nnp_fleet_config(C.Structure):
     _fields_ = [("n_vehicles", C.c_int32), ("T", C.c_int32), ("n_uniform", C.c_int32),
                 ("n_prop", C.c_int32), ("seed", C.c_uint64), ("warm_start", C.c_int32),
                 ("dt", C.c_float), ("eps_xi", C.c_float), ("eps_eta", C.c_float),
-                ("eps_phi", C.c_float), ("eps_v", C.c_float)]
+                ("eps_phi", C.c_float), ("eps_v", C.c_float), ("switch_rule", C.c_int32)]
+
+
+SWITCH_STATE, SWITCH_PLAN = 0, 1
 
 
 class nnp_vehicle_spec(C.Structure):
@@ -65,7 +68,8 @@ class Fleet:
     II); `tolerances` overrides any of eps_xi, eps_eta, eps_phi, eps_v."""
 
     def __init__(self, planner, vehicles, T: int, n_uniform: int, n_prop: int = 0,
-                 proposal=None, seed: int = 0, warm_start: bool = True, tolerances=None):
+                 proposal=None, seed: int = 0, warm_start: bool = True, tolerances=None,
+                 switch_rule: int = SWITCH_STATE):
         import torch
         self.torch = torch
         self.planner = planner
@@ -77,6 +81,7 @@ class Fleet:
         tol = dict(p, **(tolerances or {}))
         c.eps_xi, c.eps_eta, c.eps_phi, c.eps_v = (float(tol[k]) for k in
                                                    ("eps_xi", "eps_eta", "eps_phi", "eps_v"))
+        c.switch_rule = int(switch_rule)
         specs = (nnp_vehicle_spec * len(vehicles))()
         self._keep = []
         for i, v in enumerate(vehicles):

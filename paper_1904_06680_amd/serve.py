@@ -4,7 +4,10 @@ Workload: n vehicles split between the waypoint mission (after Experiment 4: fou
 alternating forward and reverse driving at full steering, no obstacles) and reverse parking into a
 2.5 x 5.5 m slot between two parked rectangles sampled as 400 points, each vehicle with its own
 random rigid placement. Every step plans with n_prop proposal draws plus n_uniform uniform draws
-over the horizon T, warm-started with the previous best parameters. Reported: per-step latency
+over the horizon T, warm-started with the previous best parameters. The cost carries the terminal
+heading and speed terms of the served preset (scenes.C4), and intermediate waypoints are passed
+once the last plan reached them over its horizon (NNP_SWITCH_PLAN, the recursive goal-setpoint
+logic of Sect. II-D); the mission completes when the vehicle itself reaches the last waypoint. Reported: per-step latency
 (host wall time of one fleet step: encoding, proposal network, batched plan, status copy; p50,
 p99, mean), rollout throughput (planned samples x T per second of step time), missions completed.
 
@@ -20,7 +23,7 @@ import time
 import numpy as np
 
 from . import learn, scenes
-from .fleet import Fleet
+from .fleet import SWITCH_PLAN, SWITCH_STATE, Fleet
 from .nnplan import Planner
 from .proposal import Proposal
 
@@ -41,11 +44,12 @@ def c4_vehicles(n: int, seed: int = 0, device=None):
 
 
 def run(planner: Planner, vehicles, kinds, steps: int, T: int, n_uniform: int, n_prop: int,
-        proposal=None, seed: int = 0, warmup: int = 3, tolerances=None, log=None) -> dict:
+        proposal=None, seed: int = 0, warmup: int = 3, tolerances=None, log=None,
+        switch_rule: int = SWITCH_PLAN) -> dict:
     """Serve `steps` sampling times; the first `warmup` steps are excluded from the latency
     statistics (workspace growth, clock ramp)."""
     fl = Fleet(planner, vehicles, T=T, n_uniform=n_uniform, n_prop=n_prop, proposal=proposal,
-               seed=seed, tolerances=tolerances)
+               seed=seed, tolerances=tolerances, switch_rule=switch_rule)
     lat, work = [], []
     t0 = time.perf_counter()
     for t in range(steps):
@@ -89,7 +93,12 @@ def main(argv=None) -> int:
     ap.add_argument("--position-only", action="store_true",
                     help="switch waypoints on position (eps_xi, eps_eta) alone")
     ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
-                    help="add the optional terminal heading / speed terms to the cost")
+                    help="weights of the terminal heading / speed terms of the cost (default: "
+                         "the served preset's 3.0 and 0.5; 0 0 gives the plain cost)")
+    ap.add_argument("--switch", choices=("plan", "state"), default="plan",
+                    help="pass intermediate waypoints once the last plan reached them over its "
+                         "horizon (plan, NNP_SWITCH_PLAN) or once the vehicle is within the "
+                         "tolerances (state)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     import torch
@@ -98,7 +107,7 @@ def main(argv=None) -> int:
     def log(*a):
         print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
 
-    preset = dict(scenes.C1)
+    preset = dict(scenes.C4)
     if args.goal_terms:
         preset.update(goal_heading_weight=args.goal_terms[0], goal_speed_weight=args.goal_terms[1])
     nt = scenes.n_theta(preset["widths"])
@@ -113,9 +122,11 @@ def main(argv=None) -> int:
     vs, kinds = c4_vehicles(args.vehicles, device=pl._dev())
     tol = dict(eps_phi=4.0, eps_v=1e3) if args.position_only else None
     res = run(pl, vs, kinds, args.steps, args.T, args.uniform, args.prop, proposal=prop,
-              tolerances=tol, log=log)
+              tolerances=tol, log=log,
+              switch_rule=SWITCH_PLAN if args.switch == "plan" else SWITCH_STATE)
+    res["switch_rule"] = args.switch
     res["tolerances"] = "position only" if args.position_only else "Table II"
-    res["goal_terms"] = args.goal_terms
+    res["goal_terms"] = [preset["goal_heading_weight"], preset["goal_speed_weight"]]
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

@@ -15,7 +15,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1904_06680_amd import learn  # noqa: E402
-from paper_1904_06680_amd.fleet import Fleet  # noqa: E402
+from paper_1904_06680_amd.fleet import SWITCH_PLAN, SWITCH_STATE, Fleet  # noqa: E402
 from paper_1904_06680_amd.nnplan import Planner, nnp_problem  # noqa: E402
 from paper_1904_06680_amd.proposal import Proposal  # noqa: E402
 
@@ -241,4 +241,51 @@ def test_fleet_steps_against_the_oracle():
             pts[i] = _move_f32(pts[i], preset["dt"])
     assert switched == 1 and wp[0] == 1
     fl.close()
+    pl.close()
+
+
+def _tolerance_margin(preset, z, goal):
+    """Signed margins of the Table II test at state z (all <= 0: within), in FP64."""
+    z = np.asarray(z, np.float64)
+    c, sn = np.cos(z[2]), np.sin(z[2])
+    gx, gy = goal[0] - z[0], goal[1] - z[1]
+    dphi = (goal[2] - z[2] + np.pi) % (2 * np.pi) - np.pi
+    return np.array([abs(c * gx + sn * gy) - preset["eps_xi"],
+                     abs(-sn * gx + c * gy) - preset["eps_eta"],
+                     abs(dphi) - preset["eps_phi"], abs(goal[3] - z[3]) - preset["eps_v"]])
+
+
+def test_fleet_plan_switching_rule():
+    """NNP_SWITCH_PLAN passes an intermediate waypoint once the step's best plan comes within the
+    Table II tolerances at some predicted state z_h, h = 1..T (checked in FP64 on the trajectory
+    of an independent nnp_plan with the same inputs); the final waypoint still needs the
+    vehicle's own state z_{t+1}; NNP_SWITCH_STATE switches only on z_{t+1}."""
+    preset = scenes.C4
+    z0 = np.zeros(4, np.float32)
+    wps = np.array([[3.0, 0.0, 0.0, 0.0], [20.0, 5.0, 0.0, 0.0]], np.float32)
+    vs = [dict(z0=z0, waypoints=wps, points=None), dict(z0=z0, waypoints=wps[:1], points=None)]
+    T, N, seed = 30, 4096, 3
+    pl = Planner(preset)
+    plan_hits = 0
+    for rule in (SWITCH_STATE, SWITCH_PLAN):
+        fl = Fleet(pl, vs, T=T, n_uniform=N, seed=seed, switch_rule=rule)
+        fl.step()
+        st = fl.state()
+        for i, v in enumerate(vs):
+            sc = scenes.Scene(z0, v["waypoints"][0], np.zeros((0, 4), np.float32), T)
+            traj = pl.plan(sc, N, seed=seed + i, inst=0)["traj"].cpu().numpy()
+            assert np.array_equal(st[i]["z"], traj[1])
+            off = np.stack([_tolerance_margin(preset, traj[h], wps[0]) for h in range(1, T + 1)])
+            hit = np.all(off <= 0, axis=1)
+            decided = np.all(np.abs(off) > 1e-5, axis=1) | ~hit     # clear at binary32 precision
+            assert decided.all(), off[~decided]
+            last = len(v["waypoints"]) == 1
+            expect = bool(hit.any()) if (rule == SWITCH_PLAN and not last) else bool(hit[0])
+            say(f"rule {rule} vehicle {i}: plan within tolerance at steps "
+                f"{(np.flatnonzero(hit) + 1).tolist()}, waypoint -> {st[i]['waypoint']}")
+            assert st[i]["waypoint"] == int(expect), (rule, i)
+            assert st[i]["done"] == (last and expect)
+            plan_hits += int(rule == SWITCH_PLAN and not last and hit.any() and not hit[0])
+        fl.close()
+    assert plan_hits == 1          # the rule made a difference on this input
     pl.close()
