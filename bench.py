@@ -28,6 +28,7 @@ N_SAMPLES, HORIZON, N_SCENES = 65536, 50, 10
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (vendor figure, packed FP32)
 FLOPS_PER_POINT_TEST = 11         # translate 2, rotate 6, squared distance 3
 FLOPS_STEP_OVERHEAD = 75          # features, control map, model, effort (transcendentals = 0)
+MINMAX_PER_POINT_TEST = 3         # max(|xi'|, |eta'|) and the two running minima
 
 
 def mlp_flops(widths) -> int:
@@ -40,6 +41,11 @@ def algorithmic_flops(N: int, T: int, P: int, widths) -> float:
     """FP32 flops of one rollout launch: N * [(T+1) * P * 11 + T * (MLP + overhead)]."""
     return float(N) * ((T + 1) * P * FLOPS_PER_POINT_TEST + T * (mlp_flops(widths)
                                                                 + FLOPS_STEP_OVERHEAD))
+
+
+def algorithmic_ops_with_minmax(N: int, T: int, P: int, widths) -> float:
+    """The same work with the point test's min/max operations counted as well (14 per test)."""
+    return algorithmic_flops(N, T, P, widths) + float(N) * (T + 1) * P * MINMAX_PER_POINT_TEST
 
 
 def source_hash() -> str:
@@ -67,6 +73,40 @@ def traffic_record(kernel_hash: str):
     if rec.get("source_hash") != kernel_hash:
         return None
     return rec.get("bytes_per_launch")
+
+
+def oracle_c0_plan() -> dict:
+    """The FP64 oracle's whole plan on the small configuration (N = 1024, T = 20, 200 points,
+    6-16-2 controller, scene 0), timed on the host cores."""
+    import oracle
+    from paper_1904_06680_amd import scenes
+    sc = scenes.scene_c0(0)
+    m = oracle.make_model(scenes.C0)
+    ob = oracle.SceneBuf(sc.z0, sc.goal, sc.a_prev_or_idle(scenes.C0), sc.points, sc.T)
+    oracle.plan(m, ob, 1024, seed=0)
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        oracle.plan(m, ob, 1024, seed=0)
+    el = (time.perf_counter() - t0) / reps
+    return {"workload": "C0 plan: N=1024, T=20, P=200, MLP 6-16-2, scene 0", "ms": round(el * 1e3, 3),
+            "value": 1024 * sc.T / el, "unit": "rollout-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle"}
+
+
+def per_scene_kernel_ms(pl, probs, reps: int = 5) -> list:
+    """Rollout-kernel device time of every scene (mean of `reps` plans each, after the timed
+    region), for the median and the worst scene."""
+    import torch
+    out = []
+    for pr, _, res in probs:
+        pl.kernel_time(reset=True)
+        for _ in range(reps):
+            pl.plan_async(pr, res)
+        torch.cuda.synchronize()
+        ms, n = pl.kernel_time(reset=True)
+        out.append(ms / max(n, 1))
+    return out
 
 
 def cpu_baseline(scene, preset, target_s: float) -> dict:
@@ -149,6 +189,7 @@ def main() -> int:
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t0
     kern_ms, launches = pl.kernel_time(reset=True)
+    scene_ms = per_scene_kernel_ms(pl, probs)
     pl.set_timing(False)
     costs = [float(probs[k][2]["cost"].item()) for k in range(min(N_SCENES, args.steps))]
 
@@ -157,11 +198,20 @@ def main() -> int:
     avg_s = kern_ms / max(launches, 1) / 1e3
     achieved = flops / avg_s / 1e12
     khash = source_hash()
+    ops_mm = algorithmic_ops_with_minmax(N_SAMPLES, HORIZON, P, preset["widths"])
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
             "traffic": traffic_record(khash), "kernel": "rollout_kernel<8-32-32-2, K=8>",
             "kernel_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops,
-            "source_hash": khash}
+            "frac_with_minmax": round(ops_mm / avg_s / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "ops_with_minmax_per_launch": ops_mm, "source_hash": khash}
+    order = sorted(range(len(scene_ms)), key=lambda i: scene_ms[i])
+    med, worst = order[len(order) // 2], order[-1]
+    per_scene = {"kernel_ms": [round(v, 4) for v in scene_ms],
+                 "median": {"scene": med, "kernel_ms": round(scene_ms[med], 4),
+                            "rollout_steps_per_s": N_SAMPLES * HORIZON / (scene_ms[med] / 1e3)},
+                 "worst": {"scene": worst, "kernel_ms": round(scene_ms[worst], 4),
+                           "rollout_steps_per_s": N_SAMPLES * HORIZON / (scene_ms[worst] / 1e3)}}
     line = {
         "metric": "rollout-steps/s (N=65536,T=50)",
         "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -174,6 +224,7 @@ def main() -> int:
                    "N": N_SAMPLES, "T": HORIZON, "P": P, "mlp": "8-32-32-2",
                    "scenes": N_SCENES, "parallelism": "single GPU"},
         "roofline": roof,
+        "per_scene": per_scene,
         "best_costs_first_scenes": [round(c, 4) for c in costs[:3]],
     }
     if not args.no_extra:
@@ -184,6 +235,7 @@ def main() -> int:
         prop.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(scs[0], preset, args.cpu_seconds)
+        line["cpu_baseline_c0"] = oracle_c0_plan()
     pl.close()
     print(json.dumps(line), flush=True)
     return 0
@@ -254,15 +306,23 @@ def bench_proposal(pl):
 
 def bench_served(pl, prop) -> dict:
     """Closed loop served: 64 vehicles (waypoint missions and reverse parking) x 200 steps, each
-    plan 8192 proposal + 8192 uniform samples over T = 50."""
+    plan 8192 proposal + 8192 uniform samples over T = 50, with the served preset's cost (terminal
+    heading and speed terms) and plan-based waypoint switching."""
     from paper_1904_06680_amd import serve
+    from paper_1904_06680_amd.nnplan import Planner
+    from paper_1904_06680_amd.scenes import C4
+    p4 = Planner(C4, device=pl.device)
     vs, kinds = serve.c4_vehicles(64, device=pl._dev())
-    r = serve.run(pl, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
-    return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50",
+    r = serve.run(p4, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
+    p4.close()
+    return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50, "
+                        "cost with terminal heading/speed terms, plan-based waypoint switching",
             "latency_ms_p50": round(r["latency_ms"]["p50"], 3),
             "latency_ms_p99": round(r["latency_ms"]["p99"], 3),
             "rollout_steps_per_s": r["rollout_steps_per_s"],
-            "missions_completed": r["missions_completed"]}
+            "missions_completed": r["missions_completed"],
+            "vehicles_per_kind": r["vehicles_per_kind"],
+            "mean_waypoints_reached": r["mean_waypoints_reached"]}
 
 
 if __name__ == "__main__":

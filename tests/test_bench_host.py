@@ -50,3 +50,18 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in r.stdout + r.stderr
+
+
+def test_algorithmic_counts_closed_form():
+    """C1 launch: 65536 x [51 x 3000 x 11 + 50 x (2 x 1344 + 66 + 75)] flops, and 3 more min/max
+    operations per point test in the inclusive count."""
+    w = (8, 32, 32, 2)
+    f = bench.algorithmic_flops(65536, 50, 3000, w)
+    assert f == 65536 * (51 * 3000 * 11 + 50 * (2 * 1344 + 66 + 75))
+    assert bench.algorithmic_ops_with_minmax(65536, 50, 3000, w) == f + 65536 * 51 * 3000 * 3
+
+
+def test_oracle_c0_plan_timing_leg():
+    r = bench.oracle_c0_plan()
+    assert r["kind"] == "oracle" and r["ms"] > 0 and r["cores"] >= 1
+    assert abs(r["value"] - 1024 * 20 / (r["ms"] / 1e3)) <= 2e-3 * r["value"]     # ms is rounded
