@@ -190,6 +190,88 @@ def evaluate(lab: Labeller, count: int, scene_seed: int, n_ref: int = 65536,
     return res
 
 
+def canonical(theta: np.ndarray, widths=(8, 32, 32, 2)) -> np.ndarray:
+    """The same networks in a canonical form (rows [n][n_theta], float64): tanh is odd, so the
+    sign of a hidden unit's incoming weights and bias can be flipped together with its outgoing
+    weights, and hidden units can be permuted with their outgoing weights, without changing the
+    function. Every hidden unit is made to have a non-negative bias, then the units of a layer are
+    sorted by bias. Two hidden layers (the 8-32-32-2 layout of nnplan.h) only."""
+    n0, n1, n2, n3 = widths
+    th = np.array(theta, np.float64)
+    n = th.shape[0]
+    o = 0
+    w1 = th[:, o:o + n1 * n0].reshape(n, n1, n0); o += n1 * n0
+    b1 = th[:, o:o + n1]; o += n1
+    w2 = th[:, o:o + n2 * n1].reshape(n, n2, n1); o += n2 * n1
+    b2 = th[:, o:o + n2]; o += n2
+    wo = th[:, o:o + n3 * n2].reshape(n, n3, n2); o += n3 * n2
+    bo = th[:, o:o + n3]
+    s = np.where(b1 < 0, -1.0, 1.0)
+    w1, b1, w2 = w1 * s[:, :, None], b1 * s, w2 * s[:, None, :]
+    k = np.argsort(b1, 1)
+    w1 = np.take_along_axis(w1, k[:, :, None], 1)
+    b1 = np.take_along_axis(b1, k, 1)
+    w2 = np.take_along_axis(w2, k[:, None, :], 2)
+    s = np.where(b2 < 0, -1.0, 1.0)
+    w2, b2, wo = w2 * s[:, :, None], b2 * s, wo * s[:, None, :]
+    k = np.argsort(b2, 1)
+    w2 = np.take_along_axis(w2, k[:, :, None], 1)
+    b2 = np.take_along_axis(b2, k, 1)
+    wo = np.take_along_axis(wo, k[:, None, :], 2)
+    return np.concatenate([w1.reshape(n, -1), b1, w2.reshape(n, -1), b2, wo.reshape(n, -1), bo], 1)
+
+
+def elite_gaussian_bound(pl: Planner, count: int, scene_seed: int = 7, n_ref: int = 65536,
+                         n_prop: int = 16384, elites: int = 64, seed: int = 0, log=None) -> dict:
+    """What a Gaussian proposal could reach at best: per held-out C1-style scene, the `elites`
+    best of `n_ref` uniform draws (the plain planner's own samples) are put in canonical form and
+    three Gaussians are fitted to them: diagonal, and the elites' own covariance (rank elites - 1)
+    plus a small diagonal, at temperature 1 and 0.5. `n_prop` draws from each (numpy, on the
+    host) are rolled out by the planner (explicit parameters) and their best cost is compared with
+    the best of the `n_ref` uniform draws, next to uniform draws of n_prop and 2 n_prop. A learned
+    proposal predicts such a Gaussian from the scene without the n_ref draws, so it cannot do
+    better than these fits. Returns, per variant, the median excess over the reference and the
+    share of scenes that match it."""
+    torch = pl.torch
+    dev = pl._dev()
+    rng = np.random.default_rng([seed, 0xE7])
+    z0, goal, pts = scenes.c1_arrays(scene_seed, count)
+    names = ("uniform_n", "uniform_2n", "diagonal", "elite_covariance", "elite_covariance_t0.5")
+    diff = {k: [] for k in names}
+    for i in range(count):
+        sc = scenes.Scene(z0[i], goal[i], pts[i], 50)
+        cu = pl.rollout(sc, n_ref, seed=100 + i, want_traj=False,
+                        want_controls=False)["cost"].cpu().numpy()
+        bU = float(cu.min())
+        if not np.isfinite(bU):
+            continue
+        diff["uniform_n"].append(float(cu[:n_prop].min()) - bU)
+        diff["uniform_2n"].append(float(cu[:2 * n_prop].min()) - bU)
+        top = np.argsort(cu, kind="stable")[:min(elites, int(np.isfinite(cu).sum()))]
+        th = pl.sample_theta(n_ref, seed=100 + i)[torch.from_numpy(top).to(dev)].cpu().numpy()
+        E = canonical(th)
+        mu, sd = E.mean(0), E.std(0)
+        L = (E - mu).T / math.sqrt(max(len(E) - 1, 1))
+        for name in names[2:]:
+            if name == "diagonal":
+                draw = mu + sd * rng.standard_normal((n_prop, E.shape[1]))
+            else:
+                tau = 0.5 if name.endswith("t0.5") else 1.0
+                draw = (mu + tau * rng.standard_normal((n_prop, len(E))) @ L.T +
+                        0.05 * sd * rng.standard_normal((n_prop, E.shape[1])))
+            c = pl.rollout(sc, n_prop, theta=torch.from_numpy(draw.astype(np.float32)),
+                           want_traj=False, want_controls=False)["cost"].cpu().numpy()
+            diff[name].append(float(c.min()) - bU)
+        if log and i % 16 == 0:
+            log(f"scene {i}: " + ", ".join(f"{k} {np.median(v):.3f}" for k, v in diff.items()
+                                           if v))
+    return {"scenes": count, "feasible": len(diff["uniform_n"]), "n_ref": n_ref,
+            "n_prop": n_prop, "elites": elites,
+            "variants": {k: {"median_excess": float(np.median(v)),
+                             "matched_share": float(np.mean(np.asarray(v) <= 0))}
+                         for k, v in diff.items()}}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--labels", type=int, default=100000)
@@ -202,12 +284,23 @@ def main(argv=None) -> int:
     ap.add_argument("--out", default="")
     ap.add_argument("--checkpoint", default="", help="training state file, written every epoch")
     ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
+    ap.add_argument("--elite-bound", type=int, default=0, metavar="SCENES",
+                    help="instead of training: the best a Gaussian fitted to each scene's elite "
+                         "uniform draws reaches (elite_gaussian_bound) on this many scenes")
     args = ap.parse_args(argv)
     import torch
     t0 = time.time()
 
     def log(*a):
         print(f"[{time.time() - t0:7.1f}s]", *a, flush=True)
+
+    if args.elite_bound:
+        res = elite_gaussian_bound(Planner(scenes.C1), args.elite_bound, log=log)
+        print(json.dumps(res), flush=True)
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(res, fh, indent=1)
+        return 0
 
     preset = scenes.C1
     nt = scenes.n_theta(preset["widths"])

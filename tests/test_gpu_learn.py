@@ -1,5 +1,5 @@
 """GPU test of the proposal's training pipeline at a small size: plain-planner labels, Adam on the
-GPU, and what the trained network gains over uniform sampling on held-out scenes.
+GPU, and the uniform fallback on held-out scenes.
 
 The fallback guarantee is exact: a plan with n proposal draws and n uniform draws contains the
 uniform plan's n draws (same seed, same Philox indices), so its best cost is never worse."""
@@ -23,7 +23,13 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_train_and_gain_small():
+def test_train_and_uniform_fallback_small():
+    """Labels from the plain planner, eight epochs of Adam (the loss falls), then held-out plans
+    with proposal draws only, uniform draws only and both: the mixed plan contains the uniform
+    plan's draws, so it is never worse than either (asserted). What the proposal gains over
+    uniform draws at matched budgets is measured (printed here, and by learn.evaluate on 256
+    held-out scenes), not asserted: on this workload it is none, and learn.elite_gaussian_bound
+    shows that no Gaussian over the parameters reaches the target."""
     nt = scenes.n_theta(scenes.C1["widths"])
     pl = Planner(scenes.C1)
     prop = Proposal(scenes.C1, nt, 512)
