@@ -228,10 +228,11 @@ def elite_gaussian_bound(pl: Planner, count: int, scene_seed: int = 7, n_ref: in
     three Gaussians are fitted to them: diagonal, and the elites' own covariance (rank elites - 1)
     plus a small diagonal, at temperature 1 and 0.5. `n_prop` draws from each (numpy, on the
     host) are rolled out by the planner (explicit parameters) and their best cost is compared with
-    the best of the `n_ref` uniform draws, next to uniform draws of n_prop and 2 n_prop. A learned
-    proposal predicts such a Gaussian from the scene without the n_ref draws, so it cannot do
-    better than these fits. Returns, per variant, the median excess over the reference and the
-    share of scenes that match it."""
+    the best of the `n_ref` uniform draws, next to uniform draws of n_prop and 2 n_prop. These
+    are the Gaussians a proposal trained on the planner's good samples can at best learn to
+    predict from the scene, which sees neither the n_ref draws nor the scene's one best sample.
+    Returns, per variant, the median excess over the reference and the share of scenes that
+    match it."""
     torch = pl.torch
     dev = pl._dev()
     rng = np.random.default_rng([seed, 0xE7])
