@@ -23,7 +23,7 @@ import sys
 import numpy as np
 
 from . import scenes
-from .fleet import Fleet
+from .fleet import SWITCH_PLAN, SWITCH_STATE, Fleet
 from .nnplan import Planner
 
 EXP5_POINTS = np.array([[-6.5, -2], [-5.5, -2], [-4.5, -2], [-3.5, -2], [-2.5, -2], [-2.5, -7],
@@ -40,9 +40,10 @@ PAPER_EXP5 = {3: dict(tau_a_s=0.088, v_kmh=(-17.3, -1.2, 16.2), path_m=(13.8, 14
 
 
 def exp5(planner: Planner, n_waypoints: int, seeds: int = 10, N: int = 65536, H: int = 200,
-         max_steps: int = 600, seed: int = 0) -> dict:
+         max_steps: int = 600, seed: int = 0, switch_rule: int = SWITCH_PLAN) -> dict:
     """One Experiment 5 mission for `seeds` vehicles (one per seed) until all are done or
-    max_steps sampling times have passed."""
+    max_steps sampling times have passed. switch_rule: when an intermediate waypoint is passed
+    (nnfleet.h; the plan rule by default)."""
     import torch
     pts = np.zeros((len(EXP5_POINTS), 4), np.float32)
     pts[:, :2] = EXP5_POINTS
@@ -50,7 +51,7 @@ def exp5(planner: Planner, n_waypoints: int, seeds: int = 10, N: int = 65536, H:
     z0 = np.array([0.0, 2.0, 0.0, 0.0], np.float32)
     vs = [dict(z0=z0, waypoints=EXP5_WAYPOINTS[n_waypoints], points=dev_pts)
           for _ in range(seeds)]
-    fl = Fleet(planner, vs, T=H, n_uniform=N, seed=seed)
+    fl = Fleet(planner, vs, T=H, n_uniform=N, seed=seed, switch_rule=switch_rule)
     states = [[z0.copy()] for _ in range(seeds)]
     lat = []
     for t in range(max_steps):
@@ -77,6 +78,7 @@ def exp5(planner: Planner, n_waypoints: int, seeds: int = 10, N: int = 65536, H:
         "infeasible_plans": int(sum(s["infeasible_steps"] for s in st)),
         "goal_heading_weight": float(planner.preset.get("goal_heading_weight", 0.0)),
         "goal_speed_weight": float(planner.preset.get("goal_speed_weight", 0.0)),
+        "switch_rule": "plan" if switch_rule == SWITCH_PLAN else "state",
         "paper": PAPER_EXP5[n_waypoints],
     }
 
@@ -88,13 +90,18 @@ def main(argv=None) -> int:
     ap.add_argument("--max-steps", type=int, default=600)
     ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
                     help="add the optional terminal heading / speed terms to the cost")
+    ap.add_argument("--switch", choices=("plan", "state"), default="plan",
+                    help="intermediate waypoints passed once the last plan reached them (plan) or "
+                         "once the vehicle is within the tolerances (state)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     preset = dict(scenes.PAPER)
     if args.goal_terms:
         preset.update(goal_heading_weight=args.goal_terms[0], goal_speed_weight=args.goal_terms[1])
     pl = Planner(preset)
-    res = [exp5(pl, w, args.seeds, args.samples, max_steps=args.max_steps) for w in (3, 2)]
+    rule = SWITCH_PLAN if args.switch == "plan" else SWITCH_STATE
+    res = [exp5(pl, w, args.seeds, args.samples, max_steps=args.max_steps, switch_rule=rule)
+           for w in (3, 2)]
     for r in res:
         print(json.dumps(r), flush=True)
     if args.out:
