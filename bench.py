@@ -242,17 +242,18 @@ def main() -> int:
 
 
 def bench_batch(pl) -> dict:
-    """256 uneven problems (N, P, T spread) in one nnp_plan_batch call; lane layout from the
+    """256 uneven problems (N, P, T spread) in one nnp_plan_batch call; launch shape from the
     autotuner. Rollout-steps/s over the wall time of the call (mean of 3 after the tuning runs)."""
     from paper_1904_06680_amd import autotune, scenes
     scs, Ns, seeds = scenes.batch_c2(0)
-    tune = autotune.tune_batch(scenes.C1, scs, Ns, seeds, candidates=(4, 8, 16), reps=3)
+    tune = autotune.tune_batch(scenes.C1, scs, Ns, seeds, reps=3)
     steps = sum(N * sc.T for sc, N in zip(scs, Ns))
     return {"workload": "256 problems, N log-uniform 4096-65536, P log-uniform 100-5000, "
                         "T in {20,40,60,80}, MLP 8-32-32-2",
             "rollout_steps": steps, "ms": round(tune["ms"], 3),
             "value": steps / (tune["ms"] / 1e3), "unit": "rollout-steps/s",
             "lanes_per_sample": tune["lanes_per_sample"],
+            "block_threads": tune["block_threads"], "tile_pairs": tune["tile_pairs"],
             "timings_ms": {k: round(v, 3) for k, v in tune["timings_ms"].items()}}
 
 

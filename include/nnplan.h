@@ -75,7 +75,11 @@ typedef struct nnp_model {
     int32_t lanes_per_sample;        /* 0 = library default for the network; 1, 2, 4, 8, 16    */
     float goal_heading_weight;       /* optional terminal terms of the cost (>= 0; 0 = off):   */
     float goal_speed_weight;         /* + w_phi |wrap(phi_g - phi_T)| + w_v |v_g - v_T|        */
-} nnp_model;
+    int32_t block_threads;           /* rollout workgroup size; 0 = default for the layout      */
+    int32_t tile_pairs;              /* point pairs per LDS buffer; 0 = default for the layout   */
+} nnp_model;                         /* (lanes_per_sample, block_threads, tile_pairs): one of   */
+                                     /* the compiled launch shapes, else NNP_EUNSUPPORTED; all  */
+                                     /* shapes give the same results bit for bit                */
 
 /* One planning problem at sampling time t (Sect. II-E, fourth comment: what is passed to the GPU
  * every t: theta source (seed), m_t^z, a_{t-1}, zeta_t^goal, m_t^ext). */

@@ -1,10 +1,11 @@
-"""Autotuner for the lane layout (samples per workgroup tile) of batched planning.
+"""Autotuner for the launch shape of batched planning.
 
-The rollout kernel comes in several layouts for one network: K lanes per sample (4, 8 or 16 for
-the 8-32-32-2 controller), which fixes the workgroup size, the samples per work item and the
-wavefronts per SIMD. All layouts give bit-identical results, so the choice is purely a matter of
-speed on the given batch shape; this module times each candidate on the caller's batch and
-returns the fastest, optionally caching the answer per device and batch signature.
+The rollout kernel is compiled in several launch shapes for one network: K lanes per sample (4, 8
+or 16 for the 8-32-32-2 controller), workgroup size (threads, hence samples per work item and
+wavefronts per CU) and LDS tile size (point pairs per buffer, hence barriers per step for large
+point sets). All shapes give bit-identical results, so the choice is purely a matter of speed on
+the given batch; this module times every compiled candidate on the caller's batch and returns the
+fastest, optionally caching the answer per device and batch signature.
 """
 from __future__ import annotations
 
@@ -24,8 +25,24 @@ def signature(preset: dict, scenes_, Ns) -> str:
     return "w{}-c{}-w{}".format("x".join(map(str, preset["widths"])), len(Ns), b(tot))
 
 
-def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: int = 3,
+# Launch shapes (lanes per sample, workgroup threads, tile pairs; 0 = the layout's default) the
+# library compiles for the 8-32-32-2 network; a shape the library does not offer is skipped.
+SHAPES = ((8, 0, 0), (4, 0, 0), (16, 0, 0), (8, 512, 4096), (8, 256, 2048))
+
+
+def _shape(c):
+    return tuple(c) + (0,) * (3 - len(c)) if isinstance(c, (tuple, list)) else (int(c), 0, 0)
+
+
+def _name(c) -> str:
+    K, rb, tp = c
+    return str(K) if rb == 0 and tp == 0 else f"{K}/{rb}/{tp}"
+
+
+def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=SHAPES, reps: int = 3,
                device: int = 0, cache: str | None = None) -> dict:
+    """Times every candidate shape (an int K or a tuple (K, block_threads, tile_pairs)) on the
+    batch; returns the fastest with all timings."""
     import torch
     dev = torch.device("cuda", device)
     key = f"{torch.cuda.get_device_name(dev)}|{signature(preset, scenes_, Ns)}"
@@ -38,9 +55,10 @@ def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: in
         except (OSError, ValueError):
             pass
     timings = {}
-    for K in candidates:
+    for c in map(_shape, candidates):
         try:
-            pl = Planner(preset, device=device, lanes_per_sample=K)
+            pl = Planner(preset, device=device, lanes_per_sample=c[0], block_threads=c[1],
+                         tile_pairs=c[2])
         except NnpError:
             continue
         probs, keep = pl.batch_problems(scenes_, Ns, seeds)
@@ -51,12 +69,13 @@ def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: in
         for _ in range(reps):
             pl.plan_batch_async(probs, outs)
         torch.cuda.synchronize(dev)
-        timings[K] = (time.perf_counter() - t0) / reps * 1e3
+        timings[c] = (time.perf_counter() - t0) / reps * 1e3
         del keep
         pl.close()
     best = min(timings, key=timings.get)
-    res = {"lanes_per_sample": best, "ms": timings[best],
-           "timings_ms": {str(k): v for k, v in timings.items()}, "key": key}
+    res = {"lanes_per_sample": best[0], "block_threads": best[1], "tile_pairs": best[2],
+           "ms": timings[best], "timings_ms": {_name(k): v for k, v in timings.items()},
+           "key": key}
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)
@@ -73,15 +92,15 @@ def tune_batch(preset: dict, scenes_, Ns, seeds, candidates=(4, 8, 16), reps: in
 
 
 def main(argv=None) -> int:
-    """Tune the lane layout on the seeded 256-problem uneven batch (`scenes.batch_c2`) and print
-    the timings; `--plans n` then plans that batch n more times with the chosen layout (the
+    """Tune the launch shape on the seeded 256-problem uneven batch (`scenes.batch_c2`) and print
+    the timings; `--plans n` then plans that batch n more times with the chosen shape (the
     command a kernel trace of the batched path runs)."""
     import argparse
 
     import torch
 
     from . import scenes
-    ap = argparse.ArgumentParser(description="lane-layout autotuner on the uneven C2 batch")
+    ap = argparse.ArgumentParser(description="launch-shape autotuner on the uneven C2 batch")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--plans", type=int, default=0)
     ap.add_argument("--cache", default="")
@@ -90,7 +109,8 @@ def main(argv=None) -> int:
     res = tune_batch(scenes.C1, scs, Ns, seeds, cache=args.cache or None)
     print(json.dumps(res), flush=True)
     if args.plans > 0:
-        pl = Planner(scenes.C1, lanes_per_sample=res["lanes_per_sample"])
+        pl = Planner(scenes.C1, lanes_per_sample=res["lanes_per_sample"],
+                     block_threads=res["block_threads"], tile_pairs=res["tile_pairs"])
         probs, keep = pl.batch_problems(scs, Ns, seeds)
         outs = [pl.alloc_result(sc.T) for sc in scs]
         for i in range(args.plans):

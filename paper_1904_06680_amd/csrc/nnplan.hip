@@ -222,12 +222,12 @@ __device__ __forceinline__ void wait_copies()
 // ---------------------------------------------------------------------------------------------
 // 2. The rollout of every sample.
 //
-// A workgroup of RB = rollout_block(K) threads holds S = RB / K samples; a sample occupies K
+// A workgroup of RB threads (the launch shape's) holds S = RB / K samples; a sample occupies K
 // adjacent lanes of one wavefront, which split its weights for the controller and its points for
 // the obstacle pass: lane q of a sample tests pairs q, q + K, q + 2K, ... of every tile against
 // the sample's own pose (every lane holds the sample's state), and the K partial minima meet
 // through DPP (exact mins: the result does not depend on K). Each step's extrapolated points
-// stream into one of two LDS buffers (at most tile_pairs(K) pairs at a time) while the other one
+// stream into one of two LDS buffers (at most TP pairs at a time) while the other one
 // is being tested; one barrier per tile publishes a buffer and frees the other. For K >= 8 the
 // workgroup's LDS also holds one slot per sample through which the controller's second hidden
 // layer receives its inputs.
@@ -235,30 +235,40 @@ __device__ __forceinline__ void wait_copies()
 constexpr int rollout_block(int K) { return K == 8 ? 512 : 256; }
 constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
 
-constexpr int rollout_waves_per_eu(int K) { return K >= 16 ? 3 : 1; }
+// Launch shape of the rollout kernels: K lanes per sample, RB threads per workgroup, TP point
+// pairs per LDS buffer (the defaults above per K; the batch autotuner chooses among the compiled
+// shapes). Every shape computes the same bits: minima are exact and the controller's sums do
+// not depend on K.
+template <int K_, int RB_ = rollout_block(K_), int TP_ = tile_pairs(K_)>
+struct Shape {
+    static constexpr int K = K_, RB = RB_, TP = TP_;
+    static constexpr int WPE = K_ >= 16 ? 3 : 1;     // wavefronts per SIMD the build aims for
+    static_assert(RB % 64 == 0 && RB % K == 0 && TP % CHUNK == 0, "whole wavefronts and chunks");
+};
 
 // LDS of one rollout workgroup.
-template <class NetT, int K>
+template <class NetT, class SH>
 struct RolloutShared {
-    static constexpr int TP = tile_pairs(K);
+    static constexpr int TP = SH::TP;
     // Hidden-layer slots, one per sample, ACT floats each at a stride padded by four floats so
     // that the float4 reads of the slots in one wavefront start on different banks.
-    static constexpr int ACT = Controller<NetT, K>::ACT;
+    static constexpr int ACT = Controller<NetT, SH::K>::ACT;
     static constexpr int ACT_STRIDE = ACT ? ACT + 4 : 0;
     v4f pbuf[2][TP];                 // point pairs of the current / next tile
-    float act[ACT ? rollout_block(K) / K * ACT_STRIDE : 4];
+    float act[ACT ? SH::RB / SH::K * ACT_STRIDE : 4];
 };
 
 // The rollout of samples [tile * S, tile * S + S) of one problem by one workgroup.
 // CENTRED: the model's rectangle is centred on the reference point (oc = 0); see Pose::point.
-template <class NetT, int K, int MODE, bool CENTRED>
+template <class NetT, class SH, int MODE, bool CENTRED>
 __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
-                                             RolloutShared<NetT, K> &sh)
+                                             RolloutShared<NetT, SH> &sh)
 {
-    constexpr int RB = rollout_block(K);
+    constexpr int K = SH::K;
+    constexpr int RB = SH::RB;
     constexpr int S = RB / K;
     constexpr int WAVES = RB / 64;
-    constexpr int TP = tile_pairs(K);
+    constexpr int TP = SH::TP;
     static_assert(ThetaSource::STAGE * RB <= 8 * TP, "weight staging fits the buffers");
     auto &pbuf = sh.pbuf;
 
@@ -337,7 +347,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
         }
         if (h < a.T) {
             float a0, a1;
-            constexpr int ACT_STRIDE = RolloutShared<NetT, K>::ACT_STRIDE;
+            constexpr int ACT_STRIDE = RolloutShared<NetT, SH>::ACT_STRIDE;
             sim.template advance<(ACT_STRIDE > 0)>(a.m, a.goal, md, a0, a1, q,
                                                    sh.act + slot * ACT_STRIDE);
             if constexpr (MODE == MODE_OUT) {
@@ -367,26 +377,26 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
 }
 
 
-template <class NetT, int K, int MODE, bool CENTRED>
-__global__ __launch_bounds__(rollout_block(K))
-__attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_kernel(const RolloutArgs a)
+template <class NetT, class SH, int MODE, bool CENTRED>
+__global__ __launch_bounds__(SH::RB)
+__attribute__((amdgpu_waves_per_eu(SH::WPE))) void rollout_kernel(const RolloutArgs a)
 {
-    __shared__ RolloutShared<NetT, K> sh;
-    rollout_tile<NetT, K, MODE, CENTRED>(a, blockIdx.x, sh);
+    __shared__ RolloutShared<NetT, SH> sh;
+    rollout_tile<NetT, SH, MODE, CENTRED>(a, blockIdx.x, sh);
 }
 
 // Many problems of uneven size in one launch: one workgroup per work item (problem, tile of S
 // samples). The host writes the items longest problems first and the dispatcher starts
 // workgroups in grid order, so short problems fill the tail. The item index comes from
 // blockIdx, so the problem descriptor is read with scalar loads, like a kernel argument.
-template <class NetT, int K, bool CENTRED>
-__global__ __launch_bounds__(rollout_block(K))
-__attribute__((amdgpu_waves_per_eu(rollout_waves_per_eu(K)))) void rollout_batch_kernel(
+template <class NetT, class SH, bool CENTRED>
+__global__ __launch_bounds__(SH::RB)
+__attribute__((amdgpu_waves_per_eu(SH::WPE))) void rollout_batch_kernel(
     const RolloutArgs *__restrict__ probs, const int2 *__restrict__ items)
 {
-    __shared__ RolloutShared<NetT, K> sh;
+    __shared__ RolloutShared<NetT, SH> sh;
     const int2 item = items[blockIdx.x];
-    rollout_tile<NetT, K, MODE_PLAN, CENTRED>(probs[item.x], item.y, sh);
+    rollout_tile<NetT, SH, MODE_PLAN, CENTRED>(probs[item.x], item.y, sh);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -541,7 +551,7 @@ __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t in
 // ---------------------------------------------------------------------------------------------
 struct Variant {
     int widths[NNP_MAX_LAYERS + 1];
-    int n_layers, feature_set, K, ntheta;
+    int n_layers, feature_set, K, block, tile, ntheta;
     void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
     void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, bool centred,
@@ -550,19 +560,19 @@ struct Variant {
     void (*launch_gather)(const RolloutArgs &, const ReplayOut &, hipStream_t);
 };
 
-template <class NetT, int K>
+template <class NetT, class SH>
 void launch_rollout_t(const RolloutArgs &a, int mode, dim3 grid, hipStream_t s)
 {
-    const dim3 block(rollout_block(K));
+    const dim3 block(SH::RB);
     const bool centred = a.m.oc == 0.0f;
     if (mode == MODE_PLAN && centred)
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, SH, MODE_PLAN, true>), grid, block, 0, s, a);
     else if (mode == MODE_PLAN)
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_PLAN, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, SH, MODE_PLAN, false>), grid, block, 0, s, a);
     else if (centred)
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, SH, MODE_OUT, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((rollout_kernel<NetT, K, MODE_OUT, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((rollout_kernel<NetT, SH, MODE_OUT, false>), grid, block, 0, s, a);
 }
 
 template <class NetT, int K>
@@ -571,16 +581,16 @@ void launch_replay_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
     hipLaunchKernelGGL((replay_kernel<NetT, K>), dim3(1), dim3(BLOCK), 0, s, a, o);
 }
 
-template <class NetT, int K>
+template <class NetT, class SH>
 void launch_rollout_batch_t(const RolloutArgs *probs, const int2 *items, int n_items,
                             bool centred, hipStream_t s)
 {
     if (centred)
-        hipLaunchKernelGGL((rollout_batch_kernel<NetT, K, true>), dim3(n_items),
-                           dim3(rollout_block(K)), 0, s, probs, items);
+        hipLaunchKernelGGL((rollout_batch_kernel<NetT, SH, true>), dim3(n_items), dim3(SH::RB),
+                           0, s, probs, items);
     else
-        hipLaunchKernelGGL((rollout_batch_kernel<NetT, K, false>), dim3(n_items),
-                           dim3(rollout_block(K)), 0, s, probs, items);
+        hipLaunchKernelGGL((rollout_batch_kernel<NetT, SH, false>), dim3(n_items), dim3(SH::RB),
+                           0, s, probs, items);
 }
 
 template <class NetT, int K>
@@ -597,17 +607,24 @@ void launch_gather_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
     hipLaunchKernelGGL((gather_kernel<NetT>), dim3(1), dim3(BLOCK), 0, s, a, o);
 }
 
-#define NNP_VARIANT(NIN, H1, H2, FEAT, K)                                                         \
-    {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, K,                              \
-     Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, K>,                  \
-     launch_replay_t<Net<NIN, H1, H2, FEAT>, K>,                                                   \
-     launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, K>,                                            \
-     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, K>, launch_gather_t<Net<NIN, H1, H2, FEAT>>}
+#define NNP_SHAPED(NIN, H1, H2, FEAT, SH)                                                         \
+    {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, SH::K, SH::RB, SH::TP,          \
+     Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, SH>,                 \
+     launch_replay_t<Net<NIN, H1, H2, FEAT>, SH::K>,                                               \
+     launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, SH>,                                           \
+     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, SH::K>, launch_gather_t<Net<NIN, H1, H2, FEAT>>}
+#define NNP_VARIANT(NIN, H1, H2, FEAT, K) NNP_SHAPED(NIN, H1, H2, FEAT, Shape<K>)
 
+using ShapeWideTile = Shape<8, 512, 4096>;      // one LDS buffer holds an 8192-point step
+using ShapeHalfBlock = Shape<8, 256, 2048>;     // two 256-thread workgroups per CU
+
+// The first listed shape of a network is its default.
 const Variant kVariants[] = {
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // two wavefronts per SIMD at 8 lanes/sample)
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 16),
+    NNP_SHAPED(8, 32, 32, NNP_FEAT_EIGHT, ShapeWideTile),
+    NNP_SHAPED(8, 32, 32, NNP_FEAT_EIGHT, ShapeHalfBlock),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 1),      // 6-16-2, 146 parameters
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 2),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 4),
@@ -616,14 +633,16 @@ const Variant kVariants[] = {
     NNP_VARIANT(5, 10, 10, NNP_FEAT_PAPER, 1),   // NN-[5,10,10,2]
 };
 
-const Variant *find_variant(const nnp_model *m, int K)
+const Variant *find_variant(const nnp_model *m, int K, int block, int tile)
 {
     for (const Variant &v : kVariants) {
         if (v.n_layers != m->n_layers || v.feature_set != m->feature_set) continue;
         bool same = true;
         for (int l = 0; l <= m->n_layers; ++l) same = same && v.widths[l] == m->widths[l];
         if (!same) continue;
-        if (K == 0 || K == v.K) return &v;   // the first listed layout is the default
+        if ((K == 0 || K == v.K) && (block == 0 || block == v.block) &&
+            (tile == 0 || tile == v.tile))
+            return &v;   // the first listed shape that matches the request
     }
     return nullptr;
 }
@@ -765,8 +784,12 @@ int check_model(const nnp_model *m, std::string &why)
         why = "lanes_per_sample must be 0, 1, 2, 4, 8 or 16";
         return NNP_EINVAL;
     }
-    if (!find_variant(m, K)) {
-        why = "no compiled kernel for this network shape and lane layout";
+    if (m->block_threads < 0 || m->tile_pairs < 0) {
+        why = "block_threads and tile_pairs must be 0 (default) or a compiled shape's value";
+        return NNP_EINVAL;
+    }
+    if (!find_variant(m, K, m->block_threads, m->tile_pairs)) {
+        why = "no compiled kernel for this network shape, lane layout and launch shape";
         return NNP_EUNSUPPORTED;
     }
     return NNP_OK;
@@ -932,7 +955,7 @@ hipEvent_t pool_event(nnp_handle *h)
 int launch_rollout(nnp_handle *h, const RolloutArgs &a, int mode, hipStream_t s)
 {
     const long long lanes = (long long)a.N * h->var->K;
-    const int rb = rollout_block(h->var->K);
+    const int rb = h->var->block;
     const dim3 grid((unsigned)((lanes + rb - 1) / rb));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->timing) {
@@ -974,7 +997,7 @@ int nnp_create(nnp_handle **out, const nnp_model *m, int device)
     if (!h) return fail(nullptr, NNP_ENOMEM, "host allocation failed");
     h->model = *m;
     h->dm = derive(m);
-    h->var = find_variant(m, m->lanes_per_sample);
+    h->var = find_variant(m, m->lanes_per_sample, m->block_threads, m->tile_pairs);
     h->device = device;
     h->err.reserve(1024);
     e = scratch_address(device, &h->scratch);
@@ -1101,7 +1124,7 @@ int nnp_plan_noalloc(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *h
         return fail_fixed(h, NNP_EDEVICE, "extrapolate_kernel launch", hipGetErrorString(e));
     // the rollout without per-sample records, then the winner re-simulated
     const long long lanes = (long long)a.N * h->var->K;
-    const int rb = rollout_block(h->var->K);
+    const int rb = h->var->block;
     h->var->launch_rollout(a, MODE_PLAN, dim3((unsigned)((lanes + rb - 1) / rb)), s);
     e = hipGetLastError();
     if (e != hipSuccess)
@@ -1133,7 +1156,7 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
         entries += table_entries(args[i]);
     }
     const int K = h->var->K;
-    const int S = rollout_block(K) / K;
+    const int S = h->var->block / K;
     // Work items, longest problems first: (problem, tile of S samples).
     std::vector<int> order((size_t)count);
     for (int i = 0; i < count; ++i) order[i] = i;

@@ -38,6 +38,7 @@ class nnp_model(C.Structure):
         ("eps_xi", C.c_float), ("eps_eta", C.c_float), ("eps_phi", C.c_float),
         ("eps_v", C.c_float), ("lanes_per_sample", C.c_int32),
         ("goal_heading_weight", C.c_float), ("goal_speed_weight", C.c_float),
+        ("block_threads", C.c_int32), ("tile_pairs", C.c_int32),
     ]
 
 
@@ -188,7 +189,8 @@ def nnp_version() -> str:
 # --------------------------------------------------------------------------------------------
 # Marshalling helpers
 # --------------------------------------------------------------------------------------------
-def make_model(p: dict, lanes_per_sample: int = 0) -> nnp_model:
+def make_model(p: dict, lanes_per_sample: int = 0, block_threads: int = 0,
+               tile_pairs: int = 0) -> nnp_model:
     m = nnp_model()
     for k in ("dt", "lf", "lr", "front", "rear", "half_width", "delta_max", "delta_rate_max",
               "u_min", "u_max", "v_min", "v_max", "norm_xi", "norm_eta", "norm_phi", "norm_v",
@@ -200,6 +202,8 @@ def make_model(p: dict, lanes_per_sample: int = 0) -> nnp_model:
         m.widths[i] = widths[i] if i < len(widths) else 0
     m.feature_set = int(p["feature_set"])
     m.lanes_per_sample = int(lanes_per_sample)
+    m.block_threads = int(block_threads)
+    m.tile_pairs = int(tile_pairs)
     m.goal_heading_weight = float(np.float32(p.get("goal_heading_weight", 0.0)))
     m.goal_speed_weight = float(np.float32(p.get("goal_speed_weight", 0.0)))
     return m
@@ -220,11 +224,12 @@ def _check(rc: int, h=None):
 class Planner:
     """A planner handle for one model on one device, fed with torch tensors."""
 
-    def __init__(self, preset: dict, device: int = 0, lanes_per_sample: int = 0):
+    def __init__(self, preset: dict, device: int = 0, lanes_per_sample: int = 0,
+                 block_threads: int = 0, tile_pairs: int = 0):
         import torch
         self.torch = torch
         self.preset = dict(preset)
-        self.model = make_model(preset, lanes_per_sample)
+        self.model = make_model(preset, lanes_per_sample, block_threads, tile_pairs)
         self.device = device
         rc, self.h = nnp_create(self.model, device)
         if rc != NNP_OK:

@@ -91,6 +91,10 @@ def _create(preset, **over):
     (dict(widths=(8, 64, 2)), nnplan.NNP_EUNSUPPORTED),                # no compiled kernel
     (dict(lanes_per_sample=3), nnplan.NNP_EINVAL),
     (dict(lanes_per_sample=1), nnplan.NNP_EUNSUPPORTED),               # 1410 weights per lane
+    (dict(block_threads=-256), nnplan.NNP_EINVAL),
+    (dict(tile_pairs=3000), nnplan.NNP_EUNSUPPORTED),                  # no such launch shape
+    (dict(lanes_per_sample=16, tile_pairs=4096), nnplan.NNP_EUNSUPPORTED),
+    (dict(block_threads=128), nnplan.NNP_EUNSUPPORTED),
 ])
 def test_invalid_models_are_rejected_before_device_work(over, code):
     rc, h = _create(scenes.C1, **over)

@@ -40,7 +40,7 @@ def mixed_batch(seed=0):
     rng = np.random.default_rng([seed, 0xBA7C])
     shapes = [(0, 64, 20), (1, 1, 1), (17, 333, 7), (3000, 2500, 50), (5000, 700, 13),
               (1537, 1200, 40), (2048, 256, 60), (120, 4096, 20), (2049, 97, 5),
-              (400, 5000, 33), (3000, 65, 50), (999, 1023, 2)]
+              (400, 5000, 33), (3000, 65, 50), (999, 1023, 2), (9000, 300, 6)]
     scs, Ns, seeds = [], [], []
     for i, (P, N, T) in enumerate(shapes):
         sc = scenes.scene_mixed(rng, P, T, name=f"mixed-{i}")
@@ -79,16 +79,20 @@ def test_batch_equals_single_plans(c1_planner):
             assert_same(ref[i], got[i], (rep, i))
 
 
-def test_batch_lane_layouts_bit_identical(c1_planner):
+def test_batch_launch_shapes_bit_identical(c1_planner):
+    """Every compiled launch shape of the 8-32-32-2 network (lanes per sample, workgroup
+    threads, LDS tile pairs) gives the same batch results, bit for bit; the mixed batch has
+    point sets of one, two and more tiles for every tile size."""
+    from paper_1904_06680_amd.autotune import SHAPES
     scs, Ns, seeds = mixed_batch(1)
-    say(f"batch lane layouts K=4,8,16: C1, {len(scs)} problems")
+    say(f"batch launch shapes {SHAPES}: C1, {len(scs)} problems")
     ref = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
-    for K in (4, 16):
-        pl = Planner(scenes.C1, lanes_per_sample=K)
+    for K, rb, tp in SHAPES[1:]:
+        pl = Planner(scenes.C1, lanes_per_sample=K, block_threads=rb, tile_pairs=tp)
         got = [np_out(o) for o in pl.plan_batch(scs, Ns, seeds)]
         pl.close()
         for i in range(len(scs)):
-            assert_same(ref[i], got[i], (K, i))
+            assert_same(ref[i], got[i], (K, rb, tp, i))
 
 
 def test_batch_c0_against_oracle():

@@ -198,13 +198,15 @@ def test_k_layouts_bit_identical():
 
 
 def test_c1_lane_layouts_bit_identical():
-    """The 8-32-32-2 controller split over 4, 8 or 16 lanes per sample gives identical bits."""
+    """The 8-32-32-2 controller in every compiled launch shape (4, 8 or 16 lanes per sample,
+    workgroup threads, LDS tile pairs) gives identical bits."""
+    from paper_1904_06680_amd.autotune import SHAPES
     sc = scenes.scene_c1(7)
     N = 1000
-    say(f"lane layouts K=4,8,16: C1 scene 7, N={N}")
+    say(f"launch shapes {SHAPES}: C1 scene 7, N={N}")
     outs = []
-    for K in (4, 8, 16):
-        pl = Planner(scenes.C1, lanes_per_sample=K)
+    for K, rb, tp in SHAPES:
+        pl = Planner(scenes.C1, lanes_per_sample=K, block_threads=rb, tile_pairs=tp)
         outs.append(np_out(pl.rollout(sc, N, seed=2)))
         plan = pl.plan(sc, N, seed=2)
         outs[-1]["plan_cost"] = plan["cost"].cpu().numpy()
