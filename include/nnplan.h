@@ -146,10 +146,11 @@ int nnp_n_theta(const nnp_handle *h);
 /* Step 5 of Alg. 1 as a plain sampler (Sect. II-E): draw N parameter vectors from Philox, roll
  * each over h = 0..T with collision checks of eq. (2) at every h, cost every sample, and return
  * the lowest-cost one (lowest index on ties) with its controls and trajectory. Every sample is
- * simulated over the whole horizon. The winner's states and controls come from per-sample
- * records the rollout writes into the handle's workspace (16 N (T+1) + 8 N T bytes, grown on demand like
- * the extrapolation table) when that size is within the handle's record limit and below 2^31
- * bytes, else from a re-simulation of the winner; both give the same bits. */
+ * simulated over the whole horizon. The winner's controls come from per-sample records of the
+ * applied controls that the rollout writes into the handle's workspace (8 N T bytes, grown on
+ * demand like the extrapolation table) and its states from z0 and those controls by the model
+ * step alone, when that size is within the handle's record limit and below 2^31 bytes; else the
+ * winner is re-simulated with its obstacle passes. Both give the same bits. */
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
 
 /* Largest per-sample record workspace nnp_plan may use (default 2^30 bytes); 0 makes every plan

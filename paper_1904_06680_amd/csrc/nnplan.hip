@@ -62,8 +62,8 @@ struct RolloutArgs {
     int P;
     const float *mu, *log_sigma;     // Gaussian proposal for samples [0, n_prop)
     int n_prop;
-    float4 *rec_traj;                // record mode: states [T+1][N] of every sample
-    float2 *rec_ctrl;                //   and controls [T][N] (step-major: coalesced stores)
+    float2 *rec_ctrl;                // record mode: applied controls [T][N] of every sample
+                                     // (step-major: coalesced stores)
 };
 
 struct ReplayOut {
@@ -290,28 +290,21 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
     if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TP), wave);
 
-    // Plan-mode records (when a.rec_traj is set) through buffer resources: base and range in
+    // Plan-mode records (when a.rec_ctrl is set) through a buffer resource: base and range in
     // scalar registers, a 32-bit lane offset, the step's offset as a scalar (the host keeps the
-    // records below 2^31 bytes).
-    const bool rec_on = MODE == MODE_PLAN && a.rec_traj != nullptr;
-    const __amdgpu_buffer_rsrc_t rec_t = __builtin_amdgcn_make_buffer_rsrc(
-        a.rec_traj, 0, rec_on ? a.N * (a.T + 1) * 16 : 0, BUFFER_RSRC_FLAGS);
+    // records below 2^31 bytes). Only the applied controls are recorded: the winner's states
+    // follow from z0 and them by the model step alone (gather_kernel), bit for bit.
+    const bool rec_on = MODE == MODE_PLAN && a.rec_ctrl != nullptr;
     const __amdgpu_buffer_rsrc_t rec_c = __builtin_amdgcn_make_buffer_rsrc(
         a.rec_ctrl, 0, rec_on ? a.N * a.T * 8 : 0, BUFFER_RSRC_FLAGS);
-    // Step h's record: z_h and a_{h-1} (the controls the model applied last, still held for the
-    // features). Issued right after the step's first wait for the copies, so the stores retire
+    // Step h's record: a_{h-1} (the controls the model applied last, still held for the
+    // features). Issued right after the step's first wait for the copies, so the store retires
     // under the point pass instead of delaying the next wait (stores count in vmcnt).
     auto record = [&](int h) {
-        if (rec_on && active && q == 0) {
-            __builtin_amdgcn_raw_buffer_store_b128(
-                u32x4{__float_as_uint(sim.x), __float_as_uint(sim.y), __float_as_uint(sim.phi),
-                      __float_as_uint(sim.v)},
-                rec_t, sample * 16, h * a.N * 16, 0);
-            if (h > 0)
-                __builtin_amdgcn_raw_buffer_store_b64(
-                    u32x2{__float_as_uint(sim.ap0), __float_as_uint(sim.ap1)}, rec_c, sample * 8,
-                    (h - 1) * a.N * 8, 0);
-        }
+        if (rec_on && active && q == 0 && h > 0)
+            __builtin_amdgcn_raw_buffer_store_b64(
+                u32x2{__float_as_uint(sim.ap0), __float_as_uint(sim.ap1)}, rec_c, sample * 8,
+                (h - 1) * a.N * 8, 0);
     };
 
     int it = 0;
@@ -495,11 +488,32 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
     int best = (int)(unsigned int)(key & 0xffffffffull);
     if (key == ~0ull || best >= a.N) best = 0;
     const float key_cost = __uint_as_float((unsigned int)(key >> 32));
-    for (int h = tid; h <= a.T; h += BLOCK) {
-        const float4 z = a.rec_traj[(size_t)h * a.N + best];
-        if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = z;
-        if (h < a.T) {
-            const float2 c = a.rec_ctrl[(size_t)h * a.N + best];
+    // the winner's recorded controls and their steering tangents, staged in LDS by the whole
+    // workgroup (T <= NNP_MAX_T): the tangent depends on the control alone, so only the part of
+    // the model step that needs the state stays in the sequential loop below
+    __shared__ float2 ctl[NNP_MAX_T];
+    __shared__ float tds[NNP_MAX_T];
+    for (int h = tid; h < a.T; h += BLOCK) {
+        const float2 c = a.rec_ctrl[(size_t)h * a.N + best];
+        ctl[h] = c;
+        tds[h] = tanf(a.m.delta_max * c.x);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // the winner's states: the model step from z0 with its recorded controls, the same
+        // device function and inputs as in the rollout, hence the same bits
+        float x = a.z0[0], y = a.z0[1], phi = a.z0[2], v = a.z0[3];
+        for (int h = 0; h <= a.T; ++h) {
+            if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = make_float4(x, y, phi, v);
+            float sv, cv;
+            sincosf(phi, &sv, &cv);
+            if (h == a.T) {
+                if (o.goal_reached)
+                    o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi,
+                                                         a.m.eps_v, a.goal, x, y, phi, v, cv, sv);
+                break;
+            }
+            const float2 c = ctl[h];
             if (o.controls) {
                 o.controls[2 * h] = c.x;
                 o.controls[2 * h + 1] = c.y;
@@ -508,14 +522,8 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
                 o.controls_phys[2 * h] = a.m.delta_max * c.x;
                 o.controls_phys[2 * h + 1] = fmaf(c.y + 1.0f, a.m.u_half_range, a.m.u_min);
             }
-        } else if (o.goal_reached) {
-            float sv, cv;
-            sincosf(z.z, &sv, &cv);
-            o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi, a.m.eps_v,
-                                                 a.goal, z.x, z.y, z.z, z.w, cv, sv);
+            model_step_td(a.m, c.y, tds[h], cv, sv, x, y, phi, v);
         }
-    }
-    if (tid == 0) {
         if (o.cost) o.cost[0] = key_cost;
         if (o.best_index) o.best_index[0] = best;
         if (o.status) o.status[0] = isinf(key_cost) ? NNP_INFEASIBLE : NNP_OK;
@@ -1061,16 +1069,14 @@ int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_strea
     if (rc) return rc;
     // records of every sample's states and controls when they fit the limit, so that the
     // winner's outputs are gathered instead of re-simulated
-    const size_t rec_need = (size_t)p->N * (size_t)(p->T + 1) * sizeof(float4) +
-                            (size_t)p->N * (size_t)p->T * sizeof(float2);
+    const size_t rec_need = (size_t)p->N * (size_t)p->T * sizeof(float2);
     const bool record = rec_need <= h->rec_limit && rec_need < (1ull << 31) &&
                         workspace_bytes(h) - h->rec_bytes + std::max(rec_need, h->rec_bytes) <=
                             h->ws_limit;
     if (record) {
         rc = grow(h, &h->d_rec, &h->rec_bytes, rec_need, s, "sample records");
         if (rc) return rc;
-        a.rec_traj = static_cast<float4 *>(h->d_rec);
-        a.rec_ctrl = reinterpret_cast<float2 *>(a.rec_traj + (size_t)p->N * (p->T + 1));
+        a.rec_ctrl = static_cast<float2 *>(h->d_rec);
     }
     rc = launch_rollout(h, a, MODE_PLAN, s);
     if (rc) return rc;

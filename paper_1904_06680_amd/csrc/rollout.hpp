@@ -394,6 +394,35 @@ __device__ __forceinline__ int within_tolerance(float eps_xi, float eps_eta, flo
            fabsf(goal[3] - v) <= eps_v;
 }
 
+// Control map and one explicit Euler step of the kinematic model (Sect. II-F, eq. (5)) with the
+// applied controls (a0, a1); c, s are the cosine and sine of the current heading.
+// cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
+// tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
+// td = tan(delta_max a0), computed by the caller (model_step) or ahead of time.
+__device__ __forceinline__ void model_step_td(const DevModel &m, float a1, float td, float c,
+                                              float s, float &x, float &y, float &phi, float &v)
+{
+    const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
+    const float tb = m.lr_over_L * td;
+    const float ds = m.dt * v;
+    const float nx = fmaf(ds, fmaf(-s, tb, c), x);
+    const float ny = fmaf(ds, fmaf(c, tb, s), y);
+    float nphi = fmaf(ds * td, m.inv_L, phi);
+    if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
+    else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
+    const float nv = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
+    x = nx;
+    y = ny;
+    phi = nphi;
+    v = nv;
+}
+
+__device__ __forceinline__ void model_step(const DevModel &m, float a0, float a1, float c,
+                                           float s, float &x, float &y, float &phi, float &v)
+{
+    model_step_td(m, a1, tanf(m.delta_max * a0), c, s, x, y, phi, v);
+}
+
 // ---------------------------------------------------------------------------------------------
 // One sample's closed-loop state.
 // ---------------------------------------------------------------------------------------------
@@ -476,9 +505,7 @@ struct SampleSim {
         }
     }
 
-    // Controller, rate limit, control map, one explicit Euler step of the kinematic model.
-    // cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
-    // tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
+    // Controller, rate limit, then the control map and the model step (model_step).
     template <bool XLDS = false>
     __device__ __forceinline__ void advance(const DevModel &m, const float (&goal)[4], float md,
                                             float &a0, float &a1, int q, float *act = nullptr)
@@ -487,22 +514,8 @@ struct SampleSim {
         features(m, goal, md, f);
         ctl.template forward<XLDS>(f, a0, a1, q, act);
         if (m.rate > 0.0f) a0 = fminf(fmaxf(a0, ap0 - m.rate), ap0 + m.rate);
-        const float delta = m.delta_max * a0;
-        const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
-        const float td = tanf(delta);
-        const float tb = m.lr_over_L * td;
-        const float ds = m.dt * v;
-        const float nx = fmaf(ds, fmaf(-s, tb, c), x);
-        const float ny = fmaf(ds, fmaf(c, tb, s), y);
-        float nphi = fmaf(ds * td, m.inv_L, phi);
-        if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
-        else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
-        const float nv = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
+        model_step(m, a0, a1, c, s, x, y, phi, v);
         effort = effort + fmaf(a0, a0, a1 * a1);
-        x = nx;
-        y = ny;
-        phi = nphi;
-        v = nv;
         ap0 = a0;
         ap1 = a1;
     }

@@ -414,7 +414,7 @@ def test_workspace_limit_enomem_and_record_fallback():
     with pytest.raises(NnpError) as ei:
         pl.plan(sc, N, seed=2)
     assert ei.value.rc == NNP_ENOMEM and "workspace limit" in str(ei.value)
-    pl.set_workspace_limit(2 << 20)        # the 1.2 MB table fits, the 5 MB of records do not
+    pl.set_workspace_limit(2 << 20)        # the 1.2 MB table fits, table + 1.6 MB of records do not
     got = np_out(pl.plan(sc, N, seed=2))
     for k in ref:
         assert np.array_equal(got[k], ref[k]), k
