@@ -488,41 +488,59 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
     int best = (int)(unsigned int)(key & 0xffffffffull);
     if (key == ~0ull || best >= a.N) best = 0;
     const float key_cost = __uint_as_float((unsigned int)(key >> 32));
-    // the winner's recorded controls and their steering tangents, staged in LDS by the whole
-    // workgroup (T <= NNP_MAX_T): the tangent depends on the control alone, so only the part of
-    // the model step that needs the state stays in the sequential loop below
+    // The winner's states from z0 and its recorded controls by the model step's own functions
+    // (same inputs, same operations, hence the same bits as in the rollout), reordered so that
+    // little stays sequential: the steering tangents and, once the heading and speed chain is
+    // known, every step's sincos are computed in parallel; the position chain comes last. Staged
+    // in LDS (T <= NNP_MAX_T).
     __shared__ float2 ctl[NNP_MAX_T];
     __shared__ float tds[NNP_MAX_T];
-    for (int h = tid; h < a.T; h += BLOCK) {
+    __shared__ float phis[NNP_MAX_T + 1], vs[NNP_MAX_T + 1], cs[NNP_MAX_T + 1], sn[NNP_MAX_T + 1];
+    const int T = a.T;
+    for (int h = tid; h < T; h += BLOCK) {
         const float2 c = a.rec_ctrl[(size_t)h * a.N + best];
         ctl[h] = c;
         tds[h] = tanf(a.m.delta_max * c.x);
+        if (o.controls) {
+            o.controls[2 * h] = c.x;
+            o.controls[2 * h + 1] = c.y;
+        }
+        if (o.controls_phys) {
+            o.controls_phys[2 * h] = a.m.delta_max * c.x;
+            o.controls_phys[2 * h + 1] = fmaf(c.y + 1.0f, a.m.u_half_range, a.m.u_min);
+        }
     }
     __syncthreads();
     if (tid == 0) {
-        // the winner's states: the model step from z0 with its recorded controls, the same
-        // device function and inputs as in the rollout, hence the same bits
-        float x = a.z0[0], y = a.z0[1], phi = a.z0[2], v = a.z0[3];
-        for (int h = 0; h <= a.T; ++h) {
-            if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = make_float4(x, y, phi, v);
-            float sv, cv;
-            sincosf(phi, &sv, &cv);
-            if (h == a.T) {
+        float phi = a.z0[2], v = a.z0[3];
+        phis[0] = phi;
+        vs[0] = v;
+        for (int h = 0; h < T; ++h) {
+            heading_speed_step(a.m, ctl[h].y, tds[h], phi, v);
+            phis[h + 1] = phi;
+            vs[h + 1] = v;
+        }
+    }
+    __syncthreads();
+    for (int h = tid; h <= T; h += BLOCK) {
+        float sv, cv;
+        sincosf(phis[h], &sv, &cv);
+        sn[h] = sv;
+        cs[h] = cv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float x = a.z0[0], y = a.z0[1];
+        for (int h = 0; h <= T; ++h) {
+            if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = make_float4(x, y, phis[h], vs[h]);
+            if (h == T) {
                 if (o.goal_reached)
                     o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi,
-                                                         a.m.eps_v, a.goal, x, y, phi, v, cv, sv);
+                                                         a.m.eps_v, a.goal, x, y, phis[T], vs[T],
+                                                         cs[T], sn[T]);
                 break;
             }
-            const float2 c = ctl[h];
-            if (o.controls) {
-                o.controls[2 * h] = c.x;
-                o.controls[2 * h + 1] = c.y;
-            }
-            if (o.controls_phys) {
-                o.controls_phys[2 * h] = a.m.delta_max * c.x;
-                o.controls_phys[2 * h + 1] = fmaf(c.y + 1.0f, a.m.u_half_range, a.m.u_min);
-            }
-            model_step_td(a.m, c.y, tds[h], cv, sv, x, y, phi, v);
+            position_step(a.m, tds[h], cs[h], sn[h], vs[h], x, y);
         }
         if (o.cost) o.cost[0] = key_cost;
         if (o.best_index) o.best_index[0] = best;

@@ -398,23 +398,37 @@ __device__ __forceinline__ int within_tolerance(float eps_xi, float eps_eta, flo
 // applied controls (a0, a1); c, s are the cosine and sine of the current heading.
 // cos(phi + beta)/cos(beta) = cos(phi) - sin(phi) tan(beta) and likewise for sin, with
 // tan(beta) = l_r tan(delta) / L, so no atan or second sincos is needed.
-// td = tan(delta_max a0), computed by the caller (model_step) or ahead of time.
-__device__ __forceinline__ void model_step_td(const DevModel &m, float a1, float td, float c,
-                                              float s, float &x, float &y, float &phi, float &v)
+// The model step in two parts, with td = tan(delta_max a0) computed by the caller (model_step)
+// or ahead of time: heading and speed (they do not depend on the position) and the position
+// (from the old heading's c, s and the old speed).
+__device__ __forceinline__ void heading_speed_step(const DevModel &m, float a1, float td,
+                                                   float &phi, float &v)
 {
     const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
+    const float ds = m.dt * v;
+    float nphi = fmaf(ds * td, m.inv_L, phi);
+    if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
+    else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
+    phi = nphi;
+    v = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
+}
+
+__device__ __forceinline__ void position_step(const DevModel &m, float td, float c, float s,
+                                              float v, float &x, float &y)
+{
     const float tb = m.lr_over_L * td;
     const float ds = m.dt * v;
     const float nx = fmaf(ds, fmaf(-s, tb, c), x);
     const float ny = fmaf(ds, fmaf(c, tb, s), y);
-    float nphi = fmaf(ds * td, m.inv_L, phi);
-    if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
-    else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
-    const float nv = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
     x = nx;
     y = ny;
-    phi = nphi;
-    v = nv;
+}
+
+__device__ __forceinline__ void model_step_td(const DevModel &m, float a1, float td, float c,
+                                              float s, float &x, float &y, float &phi, float &v)
+{
+    position_step(m, td, c, s, v, x, y);
+    heading_speed_step(m, a1, td, phi, v);
 }
 
 __device__ __forceinline__ void model_step(const DevModel &m, float a0, float a1, float c,
