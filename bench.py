@@ -310,10 +310,10 @@ def bench_served(pl, prop) -> dict:
     plan 8192 proposal + 8192 uniform samples over T = 50, with the served preset's cost (terminal
     heading and speed terms) and plan-based waypoint switching."""
     from paper_1904_06680_amd import serve
-    from paper_1904_06680_amd.nnplan import Planner
     from paper_1904_06680_amd.scenes import C4
-    p4 = Planner(C4, device=pl.device)
     vs, kinds = serve.c4_vehicles(64, device=pl._dev())
+    p4 = serve.tuned_planner(C4, vs, 50, 16384, device=pl.device)
+    shape = [p4.model.lanes_per_sample, p4.model.block_threads, p4.model.tile_pairs]
     r = serve.run(p4, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
     p4.close()
     return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50, "
@@ -323,7 +323,8 @@ def bench_served(pl, prop) -> dict:
             "rollout_steps_per_s": r["rollout_steps_per_s"],
             "missions_completed": r["missions_completed"],
             "vehicles_per_kind": r["vehicles_per_kind"],
-            "mean_waypoints_reached": r["mean_waypoints_reached"]}
+            "mean_waypoints_reached": r["mean_waypoints_reached"],
+            "launch_shape": shape}
 
 
 if __name__ == "__main__":

@@ -43,6 +43,22 @@ def c4_vehicles(n: int, seed: int = 0, device=None):
     return vs, kinds
 
 
+def tuned_planner(preset: dict, vehicles, T: int, n_samples: int, device: int = 0) -> Planner:
+    """A planner in the launch shape the autotuner picks for this fleet's batch (every vehicle's
+    first plan: start state, first waypoint, obstacles; all shapes give the same results)."""
+    from . import autotune
+    scs = []
+    for v in vehicles:
+        pts = v.get("points")
+        pts = np.zeros((0, 4), np.float32) if pts is None else pts.cpu().numpy()
+        scs.append(scenes.Scene(np.asarray(v["z0"], np.float32),
+                                np.asarray(v["waypoints"][0], np.float32), pts, T))
+    res = autotune.tune_batch(preset, scs, [n_samples] * len(scs), list(range(len(scs))),
+                              reps=2, device=device)
+    return Planner(preset, device=device, lanes_per_sample=res["lanes_per_sample"],
+                   block_threads=res["block_threads"], tile_pairs=res["tile_pairs"])
+
+
 def run(planner: Planner, vehicles, kinds, steps: int, T: int, n_uniform: int, n_prop: int,
         proposal=None, seed: int = 0, warmup: int = 3, tolerances=None, log=None,
         switch_rule: int = SWITCH_PLAN) -> dict:
@@ -121,6 +137,9 @@ def main(argv=None) -> int:
         learn.train(prop, enc[ok].contiguous(), th[ok].contiguous(), epochs=20, log=log)
     vs, kinds = c4_vehicles(args.vehicles, device=pl._dev())
     tol = dict(eps_phi=4.0, eps_v=1e3) if args.position_only else None
+    pl.close()                  # the labelling planner; the fleet gets the tuned launch shape
+    pl = tuned_planner(preset, vs, args.T, args.uniform + args.prop)
+    log(f"launch shape: {pl.model.lanes_per_sample}/{pl.model.block_threads}/{pl.model.tile_pairs}")
     res = run(pl, vs, kinds, args.steps, args.T, args.uniform, args.prop, proposal=prop,
               tolerances=tol, log=log,
               switch_rule=SWITCH_PLAN if args.switch == "plan" else SWITCH_STATE)
