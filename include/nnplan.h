@@ -77,9 +77,18 @@ typedef struct nnp_model {
     float goal_speed_weight;         /* + w_phi |wrap(phi_g - phi_T)| + w_v |v_g - v_T|        */
     int32_t block_threads;           /* rollout workgroup size; 0 = default for the layout      */
     int32_t tile_pairs;              /* point pairs per LDS buffer; 0 = default for the layout   */
-} nnp_model;                         /* (lanes_per_sample, block_threads, tile_pairs): one of   */
+                                     /* (lanes_per_sample, block_threads, tile_pairs): one of   */
                                      /* the compiled launch shapes, else NNP_EUNSUPPORTED; all  */
                                      /* shapes give the same results bit for bit                */
+    int32_t all_points;              /* 0: the obstacle pass skips groups of 64 points whose     */
+                                     /* bounding box is, for every sample of a wavefront,       */
+                                     /* beyond both the rectangle's corner distance and either  */
+                                     /* d_cap (distance features) or a bound on the step's      */
+                                     /* nearest distance carried from the previous step: such   */
+                                     /* points cannot change a collision, a margin below 1 or   */
+                                     /* the capped nearest distance; 1: every point is tested.  */
+                                     /* Same results bit for bit either way.                    */
+} nnp_model;
 
 /* One planning problem at sampling time t (Sect. II-E, fourth comment: what is passed to the GPU
  * every t: theta source (seed), m_t^z, a_{t-1}, zeta_t^goal, m_t^ext). */
@@ -171,7 +180,8 @@ int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes);
  * NNP_NOALLOC_SCRATCH_BYTES (4 MiB) that every GPU the library runs on holds until the process
  * ends; the winner's outputs are re-simulated (no per-sample records). Limit: the table of
  * (T + 1) * (P rounded up to a multiple of 64) / 2 point pairs of 16 bytes, plus 64 pairs of
- * slack and 256 bytes for the key, must fit (T = 50 allows P up to 10240); larger problems
+ * slack, the boxes of its groups of 32 pairs, the spatial order of up to 16384 points and 256
+ * bytes for the key, must fit (T = 50 allows P up to 9856); larger problems
  * return NNP_EINVAL with the sizes in nnp_last_error. The key is reset by the call itself. All
  * calls on one GPU share that GPU's array: calls that overlap on one GPU (on different streams,
  * from different threads or handles) race and must be serialised by the caller; consecutive
@@ -202,7 +212,8 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
  * extrapolated at constant velocity and tested with eq. (2) at every h = 0..T), with per-sample
  * outputs instead of the argmin: o->cost[N] (f32, +inf after any collision), o->collided[N]
  * (i32 0/1), o->first_collision[N] (i32, first step with a point inside, -1 if none),
- * o->min_margin[N] (f32, smallest normalised margin over steps and points, < 1 inside), and
+ * o->min_margin[N] (f32, smallest normalised margin over steps and points, < 1 inside; when it
+ * is requested the call tests every point, since skipped groups would leave it out), and
  * optionally o->traj[N][T+1][4] (z_h) and o->controls[N][T][2] (normalised a_h). Every output
  * pointer is a caller-owned device buffer and may be NULL (not written). Same kernel and device
  * functions as nnp_plan, so the costs are bit-identical to the ones nnp_plan minimises.

@@ -44,6 +44,13 @@ constexpr int BUFFER_RSRC_FLAGS = 0x00020000;   // buffer descriptor word 3: 32-
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
+// Point groups: every GROUP_PAIRS consecutive pairs of a step's table share a bounding box, and a
+// wavefront skips a group at a step when the box lies farther than the cull radius from every
+// one of its samples (see group_mask). Up to SORT_MAX points are first put in spatial order
+// (order_kernel) so that the groups are compact; larger sets keep the caller's order.
+constexpr int GROUP_PAIRS = 32;
+constexpr int SORT_MAX = 16384;
+constexpr int ORDER_BLOCK = 1024;
 
 struct RolloutArgs {
     DevModel m;
@@ -64,6 +71,18 @@ struct RolloutArgs {
     int n_prop;
     float2 *rec_ctrl;                // record mode: applied controls [T][N] of every sample
                                      // (step-major: coalesced stores)
+    const float4 *bb;                // [T+1][P2 / GROUP_PAIRS] group boxes (xmin, ymin, xmax, ymax)
+    uint32_t *perm;                  // [P] spatial order of the points, or null (caller's order)
+    float *disp;                     // [1] bound on a point's move between two steps (order_kernel)
+    float cull_r2;                   // squared cull radius; +INFINITY tests every group
+    float coll_r2;                   // squared collision radius (the rectangle's corner distance)
+    float step_scale;                // bound on |z_{h+1} - z_h| (x, y) per unit of |v_h|
+};
+
+// Culling constants of a model (cull_consts): squared cull and collision radii, and the bound on
+// the sample's move per step per unit of speed.
+struct CullConsts {
+    float cull_r2, coll_r2, step_scale;
 };
 
 struct ReplayOut {
@@ -76,22 +95,56 @@ enum { MODE_PLAN = 0, MODE_OUT = 1 };
 // ---------------------------------------------------------------------------------------------
 // 1. Constant-velocity extrapolation table; padding repeats the last point (min-neutral).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__restrict__ pts, int P,
-                                                            int P2, int T, float dt,
+static_assert((POINT_PAD / 2) % GROUP_PAIRS == 0, "a step's pairs form whole groups");
+
+// Entry (h, j) of the table (pair j of step h, entries numbered h * P2 + j) and the boxes of the
+// point groups: P2 is a multiple of GROUP_PAIRS, so the pairs of one group sit in one aligned
+// half-wavefront, whose lanes reduce their coordinates (exact minima and maxima); the group's
+// first lane writes the box. NaN coordinates are left out of a box, as the obstacle pass leaves
+// them out of its minima. The caller runs whole half-wavefronts.
+__device__ __forceinline__ void table_entry(const float4 *__restrict__ pts,
+                                            const uint32_t *__restrict__ perm, int P, int P2,
+                                            float dt, long long gid, float4 *__restrict__ ext,
+                                            float4 *__restrict__ bb)
+{
+    const int h = (int)(gid / P2);
+    const int j = (int)(gid % P2);
+    const float t = (float)h * dt;
+    int i0 = min(2 * j, P - 1), i1 = min(2 * j + 1, P - 1);
+    if (perm) {
+        i0 = (int)perm[i0];
+        i1 = (int)perm[i1];
+    }
+    const float4 a = pts[i0];
+    const float4 b = pts[i1];
+    const float4 e = make_float4(fmaf(t, a.z, a.x), fmaf(t, a.w, a.y), fmaf(t, b.z, b.x),
+                                 fmaf(t, b.w, b.y));
+    ext[gid] = e;
+    float lx = fminf(e.x, e.z), ly = fminf(e.y, e.w), hx = fmaxf(e.x, e.z), hy = fmaxf(e.y, e.w);
+#pragma unroll
+    for (int off = GROUP_PAIRS / 2; off >= 1; off >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, off, 64));
+        ly = fminf(ly, __shfl_xor(ly, off, 64));
+        hx = fmaxf(hx, __shfl_xor(hx, off, 64));
+        hy = fmaxf(hy, __shfl_xor(hy, off, 64));
+    }
+    if (j % GROUP_PAIRS == 0)
+        bb[(size_t)h * (P2 / GROUP_PAIRS) + j / GROUP_PAIRS] = make_float4(lx, ly, hx, hy);
+}
+
+__global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__restrict__ pts,
+                                                            const uint32_t *__restrict__ perm,
+                                                            int P, int P2, int T, float dt,
                                                             float4 *__restrict__ ext,
+                                                            float4 *__restrict__ bb,
                                                             unsigned long long *best_key)
 {
     const long long n = (long long)(T + 1) * P2;
     const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (gid == 0 && best_key) *best_key = ~0ull;
+    // n and the block size are multiples of GROUP_PAIRS: lanes leave in whole half-wavefronts
     if (gid >= n || P == 0) return;
-    const int h = (int)(gid / P2);
-    const int j = (int)(gid % P2);
-    const float t = (float)h * dt;
-    const float4 a = pts[min(2 * j, P - 1)];
-    const float4 b = pts[min(2 * j + 1, P - 1)];
-    ext[gid] = make_float4(fmaf(t, a.z, a.x), fmaf(t, a.w, a.y), fmaf(t, b.z, b.x),
-                           fmaf(t, b.w, b.y));
+    table_entry(pts, perm, P, P2, dt, gid, ext, bb);
 }
 
 // The same table for every problem of a batch: blockIdx.y is the problem, the x blocks stride
@@ -103,16 +156,149 @@ __global__ __launch_bounds__(BLOCK) void extrapolate_batch_kernel(const RolloutA
     if (a.P == 0) return;
     const long long n = (long long)(a.T + 1) * a.P2;
     float4 *ext = const_cast<float4 *>(a.ext);
+    float4 *bb = const_cast<float4 *>(a.bb);
     for (long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x; gid < n;
-         gid += (long long)gridDim.x * BLOCK) {
-        const int h = (int)(gid / a.P2);
-        const int j = (int)(gid % a.P2);
-        const float t = (float)h * a.m.dt;
-        const float4 p = a.obst[min(2 * j, a.P - 1)];
-        const float4 q = a.obst[min(2 * j + 1, a.P - 1)];
-        ext[gid] = make_float4(fmaf(t, p.z, p.x), fmaf(t, p.w, p.y), fmaf(t, q.z, q.x),
-                               fmaf(t, q.w, q.y));
+         gid += (long long)gridDim.x * BLOCK)
+        table_entry(a.obst, a.perm, a.P, a.P2, a.m.dt, gid, ext, bb);
+}
+
+// Spread the low 16 bits of v over the even bit positions (one half of a Z-order key).
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v)
+{
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Spatial order of P <= SORT_MAX points, by one workgroup of ORDER_BLOCK threads: each point's
+// position at the middle of the horizon (tmid), on a 512 x 512 grid over the bounding box of
+// those positions, gives an 18-bit Z-order key; with the point index in the low 14 bits every
+// key is unique, so a bitonic sort in LDS gives one deterministic order. perm[i] is the index of
+// the i-th point in it. No result depends on the order (the obstacle pass takes exact minima);
+// it keeps the points of a group close together, so that their box is small.
+//
+// It also writes *disp, a bound on how far any point of the table moves between two consecutive
+// steps: |p_h - p_{h-1}| <= |v| (t_h - t_{h-1}) plus the rounding of the two table entries, with
+// t_h = fl(h dt) (at most one ulp of T dt off, a relative 5e-4 of dt for T <= 4096) and entries
+// no larger than M = max(|x| + T dt |vx|, |y| + T dt |vy|) (half an ulp each, per axis).
+// Non-finite inputs give +INFINITY.
+__device__ void order_points(const float4 *__restrict__ pts, int P, float tmid, float span,
+                             float dt, uint32_t *__restrict__ perm, float *__restrict__ disp,
+                             uint32_t *keys, float (&red)[6][ORDER_BLOCK / 64])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    float lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY, v2 = 0.0f, pm = 0.0f;
+    bool bad = false;
+    for (int i = tid; i < P; i += ORDER_BLOCK) {
+        const float4 p = pts[i];
+        const float x = fmaf(tmid, p.z, p.x), y = fmaf(tmid, p.w, p.y);
+        lx = fminf(lx, x);
+        ly = fminf(ly, y);
+        hx = fmaxf(hx, x);
+        hy = fmaxf(hy, y);
+        const float s2 = fmaf(p.z, p.z, p.w * p.w);
+        const float m = fmaxf(fmaf(span, fabsf(p.z), fabsf(p.x)), fmaf(span, fabsf(p.w), fabsf(p.y)));
+        bad = bad || !(s2 < INFINITY) || !(m < INFINITY);
+        v2 = fmaxf(v2, s2);
+        pm = fmaxf(pm, m);
     }
+    if (bad) v2 = INFINITY;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        lx = fminf(lx, __shfl_xor(lx, off, 64));
+        ly = fminf(ly, __shfl_xor(ly, off, 64));
+        hx = fmaxf(hx, __shfl_xor(hx, off, 64));
+        hy = fmaxf(hy, __shfl_xor(hy, off, 64));
+        v2 = fmaxf(v2, __shfl_xor(v2, off, 64));
+        pm = fmaxf(pm, __shfl_xor(pm, off, 64));
+    }
+    if (lane == 0) {
+        red[0][wave] = lx;
+        red[1][wave] = ly;
+        red[2][wave] = hx;
+        red[3][wave] = hy;
+        red[4][wave] = v2;
+        red[5][wave] = pm;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < ORDER_BLOCK / 64; ++w) {
+        lx = fminf(lx, red[0][w]);
+        ly = fminf(ly, red[1][w]);
+        hx = fmaxf(hx, red[2][w]);
+        hy = fmaxf(hy, red[3][w]);
+        v2 = fmaxf(v2, red[4][w]);
+        pm = fmaxf(pm, red[5][w]);
+    }
+    if (tid == 0) {
+        const float d = fmaf(sqrtf(v2) * dt, 1.001f, pm * 0x1p-21f);
+        *disp = d < INFINITY ? d : INFINITY;
+    }
+    // grid scales (0 when the extent is empty or not finite: every key then has cell 0)
+    const float sx = hx > lx ? 511.0f / (hx - lx) : 0.0f;
+    const float sy = hy > ly ? 511.0f / (hy - ly) : 0.0f;
+    int n = 2;
+    while (n < P) n <<= 1;
+    for (int i = tid; i < n; i += ORDER_BLOCK) {
+        uint32_t k = 0xFFFFFFFFu;          // padding sorts last (no real key reaches it: i < 16383)
+        if (i < P) {
+            const float4 p = pts[i];
+            const float x = fmaf(tmid, p.z, p.x), y = fmaf(tmid, p.w, p.y);
+            // fmaxf(NaN, 0) = 0: non-finite positions fall into cell 0
+            const uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), 511.0f);
+            const uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), 511.0f);
+            k = ((spread_bits(cx) | (spread_bits(cy) << 1)) << 14) | (uint32_t)i;
+        }
+        keys[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < (n >> 1); t += ORDER_BLOCK) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const uint32_t u = keys[lo], v = keys[hi];
+                if ((u > v) == ((lo & size) == 0)) {   // ascending where bit `size` of lo is 0
+                    keys[lo] = v;
+                    keys[hi] = u;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < P; i += ORDER_BLOCK) perm[i] = keys[i] & 0x3FFFu;
+}
+
+// The order and the displacement bound of one problem; a problem with more than SORT_MAX points
+// keeps the caller's order and has no bound (+INFINITY: its culling uses the radius alone).
+__device__ __forceinline__ void order_problem(const RolloutArgs &a, uint32_t *keys,
+                                              float (&red)[6][ORDER_BLOCK / 64])
+{
+    if (!a.perm) {
+        if (threadIdx.x == 0) *a.disp = INFINITY;
+        return;
+    }
+    const float span = (float)a.T * a.m.dt;
+    order_points(a.obst, a.P, 0.5f * span, span, a.m.dt, a.perm, a.disp, keys, red);
+}
+
+__global__ __launch_bounds__(ORDER_BLOCK) void order_kernel(const RolloutArgs a)
+{
+    __shared__ uint32_t keys[SORT_MAX];
+    __shared__ float red[6][ORDER_BLOCK / 64];
+    order_problem(a, keys, red);
+}
+
+// One workgroup per problem of a batch.
+__global__ __launch_bounds__(ORDER_BLOCK) void order_batch_kernel(const RolloutArgs *probs)
+{
+    __shared__ uint32_t keys[SORT_MAX];
+    __shared__ float red[6][ORDER_BLOCK / 64];
+    const RolloutArgs &a = probs[blockIdx.x];
+    if (a.P > 0) order_problem(a, keys, red);
 }
 
 template <class NetT>
@@ -156,62 +342,168 @@ __device__ __forceinline__ float wave_min_f(float v)
     return v;
 }
 
-// The obstacle pass of one lane: n point pairs p[0], p[STRIDE], ..., p[(n - 1) STRIDE] in LDS
-// (n a multiple of G) against one pose. The K lanes of a sample take every K-th pair from
-// consecutive start pairs, so one wavefront instruction reads K consecutive pairs (K x 16 bytes
-// on distinct banks), each broadcast to the 64 / K samples of the wavefront.
-// Two register groups of G pairs alternate: one is read while the other is tested, so the
-// LDS latency hides behind the arithmetic even at one wavefront per SIMD (G pairs per group:
-// four at one or two wavefronts per SIMD, two at three, where registers are short). The empty asm
-// statements consume a group (forcing its wait there), and the scheduling barriers keep the
-// compiler from sinking the reads next to their uses.
-template <int G, bool CENTRED, int STRIDE>
-__device__ __forceinline__ void point_pass(const Pose &pose, const v4f *p, int n, float &mm,
-                                           float &md)
+// Wavefront-wide mask of the groups of a tile segment that some sample of this wavefront needs:
+// bit g for the group whose box is boxes[g] (g < ng <= 64). A sample needs a group unless the
+// squared distance from its reference point (x, y) to the box exceeds r2; the K lanes of a
+// sample test K groups at a time, and the wavefront's ballot is folded over its 64 / K samples.
+// The box distance is a lower bound of the distance to every point of the group (up to a few
+// rounding errors, which the host's margin in r2 covers), so a skipped group holds no point the
+// obstacle pass could count: no minimum changes.
+template <int K>
+__device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x, float y,
+                                               float r2, int q)
 {
-    static_assert(G == 2 || G == 4, "groups of two or four pairs");
-    v4f a[G];
+    static_assert(64 % K == 0 && K <= 16, "whole samples per wavefront");
+    constexpr int R = 64 / K;      // rounds for a full segment; the boxes past ng are read (in
+    uint64_t need = 0;             // bounds) and masked off, so the reads need no branches
 #pragma unroll
-    for (int g = 0; g < G; ++g) a[g] = p[g * STRIDE];
-    int i = 0;
-    for (; i + 2 * G <= n; i += 2 * G) {
+    for (int r = 0; r < R; ++r) {
+        const v4f b = boxes[r * K + q];
+        const float ex = fmaxf(fmaxf(b.x - x, x - b.z), 0.0f);
+        const float ey = fmaxf(fmaxf(b.y - y, y - b.w), 0.0f);
+        const float d2 = fmaf(ex, ex, ey * ey);
+        uint64_t m = __ballot(!(d2 > r2));       // NaN counts as near
+#pragma unroll
+        for (int sh = 32; sh >= K; sh >>= 1) m |= m >> sh;
+        need |= (m & ((1ull << K) - 1)) << (r * K);
+    }
+    return ng >= 64 ? need : need & ((1ull << ng) - 1);
+}
+
+// The obstacle pass of one lane over the groups of a tile segment marked in `need`, against one
+// pose. The K = STRIDE lanes of a sample split the points: chunk c of the segment is the lane's
+// pairs p[(c G + g) STRIDE], g < G, so one wavefront instruction reads K consecutive pairs (K x 16
+// bytes on distinct banks), each broadcast to the 64 / K samples of the wavefront; a group is
+// CPG chunks. The chunks of the marked groups are visited in order with two register groups of
+// G pairs that alternate: one is read while the other is tested, so the LDS latency hides behind
+// the arithmetic even at one wavefront per SIMD (G = 4 at one or two wavefronts per SIMD, 2 at
+// three, where registers are short). The empty asm statements consume a group (forcing its wait
+// there), and the scheduling barriers keep the compiler from sinking the reads next to their
+// uses. The walk over the mask is wavefront-uniform (scalar) control: with one chunk per group,
+// a find-first-set and a bit clear per chunk. In the general walk the last step reads the
+// current chunk again instead of a next one (in bounds, unused).
+template <int G, bool CENTRED, int STRIDE>
+__device__ __forceinline__ void point_pass_groups(const Pose &pose, const v4f *p, uint64_t need,
+                                                  float &mm, float &md)
+{
+    constexpr int CPG = GROUP_PAIRS / (STRIDE * G);
+    static_assert(CPG >= 1 && CPG * STRIDE * G == GROUP_PAIRS, "whole chunks per group");
+    if (!need) return;
+    if constexpr (CPG == 1) {
+        // one chunk per group: the walk is a find-first-set and a bit clear per chunk
+        int j = __builtin_ctzll(need);
+        need &= ~(1ull << j);
+        v4f a[G], b[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) a[g] = p[(j * G + g) * STRIDE];
+        for (;;) {
+            if constexpr (G == 4) asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]));
+            else asm volatile("" ::"v"(a[0]), "v"(a[1]));
+            if (!need) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
+                return;
+            }
+            j = __builtin_ctzll(need);
+            need &= ~(1ull << j);
+#pragma unroll
+            for (int g = 0; g < G; ++g) b[g] = p[(j * G + g) * STRIDE];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (G == 4) asm volatile("" ::"v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
+            else asm volatile("" ::"v"(b[0]), "v"(b[1]));
+            if (!need) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) pose.pair<CENTRED>(b[g], mm, md);
+                return;
+            }
+            j = __builtin_ctzll(need);
+            need &= ~(1ull << j);
+#pragma unroll
+            for (int g = 0; g < G; ++g) a[g] = p[(j * G + g) * STRIDE];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < G; ++g) pose.pair<CENTRED>(b[g], mm, md);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    int j = __builtin_ctzll(need);
+    need &= need - 1;
+    int ca = j * CPG, end = ca + CPG, cb;
+    v4f a[G], b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) a[g] = p[(ca * G + g) * STRIDE];
+    for (;;) {
         if constexpr (G == 4) asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]));
         else asm volatile("" ::"v"(a[0]), "v"(a[1]));
-        v4f b[G];
+        bool more = true;
+        cb = ca + 1;
+        if (cb == end) {
+            if (need) {
+                j = __builtin_ctzll(need);
+                need &= need - 1;
+                cb = j * CPG;
+                end = cb + CPG;
+            } else {
+                more = false;
+                cb = ca;
+            }
+        }
 #pragma unroll
-        for (int g = 0; g < G; ++g) b[g] = p[(i + G + g) * STRIDE];
+        for (int g = 0; g < G; ++g) b[g] = p[(cb * G + g) * STRIDE];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (G == 4) asm volatile("" ::"v"(b[0]), "v"(b[1]), "v"(b[2]), "v"(b[3]));
         else asm volatile("" ::"v"(b[0]), "v"(b[1]));
-        const int na = i + 2 * G < n ? i + 2 * G : i;
+        if (!more) break;
+        ca = cb + 1;
+        if (ca == end) {
+            if (need) {
+                j = __builtin_ctzll(need);
+                need &= need - 1;
+                ca = j * CPG;
+                end = ca + CPG;
+            } else {
+                more = false;
+                ca = cb;
+            }
+        }
 #pragma unroll
-        for (int g = 0; g < G; ++g) a[g] = p[(na + g) * STRIDE];
+        for (int g = 0; g < G; ++g) a[g] = p[(ca * G + g) * STRIDE];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int g = 0; g < G; ++g) pose.pair<CENTRED>(b[g], mm, md);
         __builtin_amdgcn_sched_barrier(0);
-    }
-    if (i < n) {            // a last group when n is G more than a multiple of 2G
-#pragma unroll
-        for (int g = 0; g < G; ++g) pose.pair<CENTRED>(a[g], mm, md);
+        if (!more) {
+            if constexpr (G == 4) asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]));
+            else asm volatile("" ::"v"(a[0]), "v"(a[1]));
+            break;
+        }
     }
 }
 
-// Asynchronous copy of `cnt` point pairs (rounded up to whole chunks of 64) from global memory
-// into an LDS buffer: each wavefront instruction moves one chunk, lane l the pair l of it, with
-// no register staging. Completion is awaited with vmcnt before the barrier that publishes the
-// buffer.
+// Asynchronous copy of `cnt` 16-byte entries (point pairs or group boxes) from global memory
+// into an LDS buffer, in chunks of 64: each wavefront instruction moves one chunk, lane l entry l
+// of it, with no register staging. The source is a buffer resource of exactly `cnt` entries (in
+// scalar registers), so the lanes of a last partial chunk read zeros, never memory past the
+// table, and the lane's byte offset is the only vector register the copies hold. Chunk c is
+// moved by wavefront (first + c) mod WAVES (`wave` is wavefront-uniform). Completion is awaited
+// with vmcnt before the barrier that publishes the buffer.
 template <int WAVES>
-__device__ __forceinline__ void copy_points(const v4f *src, v4f *dst, int cnt, int wave)
+__device__ __forceinline__ void copy_entries(const v4f *src, v4f *dst, int cnt, int first,
+                                             int wave)
 {
-    const int lane = threadIdx.x & 63;
-    for (int c = wave; c * CHUNK < cnt; c += WAVES)
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(src + c * CHUNK + lane),
-            (__attribute__((address_space(3))) void *)(dst + c * CHUNK), 16, 0, 0);
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<v4f *>(src), 0, cnt * 16, BUFFER_RSRC_FLAGS);
+    const unsigned vo = (threadIdx.x & 63) * 16u;
+    for (int c = (wave - first + WAVES) % WAVES; c * CHUNK < cnt; c += WAVES)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            r, (__attribute__((address_space(3))) void *)(dst + c * CHUNK), 16, vo,
+            c * CHUNK * 16, 0, 0);
 }
 
 __device__ __forceinline__ void wait_copies()
@@ -255,6 +547,9 @@ struct RolloutShared {
     static constexpr int ACT = Controller<NetT, SH::K>::ACT;
     static constexpr int ACT_STRIDE = ACT ? ACT + 4 : 0;
     v4f pbuf[2][TP];                 // point pairs of the current / next tile
+    // their groups' boxes (whole copy chunks: a copy moves CHUNK entries)
+    static constexpr int BOXES = (TP / GROUP_PAIRS + CHUNK - 1) / CHUNK * CHUNK;
+    v4f bbuf[2][BOXES];
     float act[ACT ? SH::RB / SH::K * ACT_STRIDE : 4];
 };
 
@@ -273,7 +568,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
     auto &pbuf = sh.pbuf;
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = (tid & 63) % K;
     const int slot = tid / K;
     const int sample = tile * S + slot;
@@ -288,7 +583,19 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
     const int P2 = a.P2;
     const int ntile = (P2 + TP - 1) / TP;                      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
-    if (ntile > 0) copy_points<WAVES>(ext, pbuf[0], min(P2, TP), wave);
+    const int NG = P2 / GROUP_PAIRS;                           // groups per step
+    constexpr int TG = TP / GROUP_PAIRS;                       // groups per full tile
+    static_assert(TP % GROUP_PAIRS == 0, "whole groups per tile");
+    const v4f *bbs = reinterpret_cast<const v4f *>(a.bb);
+    const bool cull = a.cull_r2 < INFINITY;
+    auto copy_tile = [&](int h, int t, int buf) {
+        const int n = min(TP, P2 - t * TP);
+        copy_entries<WAVES>(ext + (size_t)h * P2 + (size_t)t * TP, pbuf[buf], n, 0, wave);
+        if (cull)   // the boxes by the last wavefronts: the point chunks start at the first
+            copy_entries<WAVES>(bbs + (size_t)h * NG + (size_t)t * TG, sh.bbuf[buf],
+                                n / GROUP_PAIRS, WAVES - 1, wave);
+    };
+    if (ntile > 0) copy_tile(0, 0, 0);
 
     // Plan-mode records (when a.rec_ctrl is set) through a buffer resource: base and range in
     // scalar registers, a 32-bit lane offset, the step's offset as a scalar (the host keeps the
@@ -307,30 +614,52 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
                 (h - 1) * a.N * 8, 0);
     };
 
+    // Culling threshold of a step (per sample): the cull radius, lowered by a bound on the
+    // step's nearest squared distance. The point p that was nearest at the previous step (or any
+    // point at that distance) is now at most sqrt(md) + |dz| + disp away, where |dz| <= |v|
+    // step_scale (plus half an ulp of x and y) is the sample's move and disp the points' move.
+    // A group whose box is farther than that bound holds no point nearer than p, and p's own
+    // group is never skipped, so the minimum over the tested points is the minimum over all;
+    // the collision radius is kept as a floor, so no point that could be inside is skipped.
+    // The factor 1.00001 covers the rounding of the bound, of the box distance and of the
+    // points' squared distances (a few float ulps each).
+    const float disp = cull ? *a.disp : INFINITY;
+    float bnd = INFINITY;
+
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
         const Pose pose = sim.begin_step(a.m);
+        const float thr = bnd < a.cull_r2 ? fmaxf(a.coll_r2, bnd) : a.cull_r2;
         float mm = INFINITY, md = INFINITY;
         for (int t = 0; t < ntile; ++t, ++it) {
             wait_copies();
             __syncthreads();            // buffer it & 1 ready; everyone is done with the other
             // the next tile in sequence streams into the other buffer: tile t + 1 of this step,
             // else the first tile of the next step
-            if (t + 1 < ntile)
-                copy_points<WAVES>(ext + (size_t)h * P2 + (size_t)(t + 1) * TP,
-                                   pbuf[(it + 1) & 1], min(TP, P2 - (t + 1) * TP), wave);
-            else if (h < a.T)
-                copy_points<WAVES>(ext + (size_t)(h + 1) * P2, pbuf[(it + 1) & 1], min(P2, TP),
-                                   wave);
+            if (t + 1 < ntile) copy_tile(h, t + 1, (it + 1) & 1);
+            else if (h < a.T) copy_tile(h + 1, 0, (it + 1) & 1);
             if constexpr (MODE == MODE_PLAN)
                 if (t == 0) record(h);
-            const int n_sub = min(TP, P2 - t * TP) / K;       // multiple of 2 (of 4 for K <= 8)
-            point_pass<(K >= 16 ? 2 : 4), CENTRED, K>(pose, pbuf[it & 1] + q, n_sub, mm, md);
+            // the tile's groups in segments of at most 64 (one mask word each)
+            const int ngt = min(TP, P2 - t * TP) / GROUP_PAIRS;
+            for (int g0 = 0; g0 < ngt; g0 += 64) {
+                const int ng = min(64, ngt - g0);
+                const uint64_t need =
+                    cull ? group_mask<K>(sh.bbuf[it & 1] + g0, ng, pose.x, pose.y, thr, q)
+                         : (ng >= 64 ? ~0ull : (1ull << ng) - 1);
+                point_pass_groups<(K >= 16 ? 2 : 4), CENTRED, K>(
+                    pose, pbuf[it & 1] + g0 * GROUP_PAIRS + q, need, mm, md);
+            }
         }
         if constexpr (MODE == MODE_PLAN)
             if (ntile == 0) record(h);
         mm = group_min<K>(mm);
         md = group_min<K>(md);
+        if (cull) {
+            const float reach = sqrtf(md) + fmaf(fabsf(sim.v), a.step_scale, disp) +
+                                (fabsf(sim.x) + fabsf(sim.y)) * 0x1p-22f;
+            bnd = reach * reach * 1.00001f;    // +INFINITY or NaN: the radius alone next step
+        }
         sim.record_collision(h, mm);
         if constexpr (MODE == MODE_OUT) {
             if (a.traj && active && q == 0) {
@@ -716,8 +1045,9 @@ struct nnp_handle {
     const Variant *var;
     int device;
     unsigned long long *d_key = nullptr;
-    float4 *d_ext = nullptr;
+    float4 *d_ext = nullptr;           // extrapolation table, group boxes, spatial order
     size_t ext_bytes = 0;
+    CullConsts cull;                   // culling constants of the model (cull_consts)
     // per-sample records of nnp_plan (states and controls of every sample)
     void *d_rec = nullptr;
     size_t rec_bytes = 0;
@@ -810,6 +1140,10 @@ int check_model(const nnp_model *m, std::string &why)
         why = "lanes_per_sample must be 0, 1, 2, 4, 8 or 16";
         return NNP_EINVAL;
     }
+    if (m->all_points != 0 && m->all_points != 1) {
+        why = "all_points must be 0 or 1";
+        return NNP_EINVAL;
+    }
     if (m->block_threads < 0 || m->tile_pairs < 0) {
         why = "block_threads and tile_pairs must be 0 (default) or a compiled shape's value";
         return NNP_EINVAL;
@@ -819,6 +1153,38 @@ int check_model(const nnp_model *m, std::string &why)
         return NNP_EUNSUPPORTED;
     }
     return NNP_OK;
+}
+
+// Culling constants of the obstacle pass (all +INFINITY with all_points: every point tested).
+// A point can change a sample's minima at a step only if it lies within R of the reference
+// point: a margin below 1 means inside the rectangle, hence within its corner distance rc, and
+// the distance features are constant (d_cap) beyond d_cap. Relative margins of 1e-3 on rc and
+// 1e-5 on the squares cover the rounding of the box distance, of the point test and of the
+// pose's sine and cosine (a few float ulps each). step_scale bounds the sample's move in one
+// step per unit of speed: the model moves the reference point by dt |v| sqrt(1 + tan(beta)^2)
+// with tan(beta) = l_r tan(delta) / L and |delta| <= delta_max.
+float round_up_f(double v)
+{
+    const float f = (float)v;
+    return (double)f >= v ? f : nextafterf(f, INFINITY);
+}
+
+CullConsts cull_consts(const nnp_model *m)
+{
+    CullConsts c = {INFINITY, INFINITY, INFINITY};
+    if (m->all_points) return c;
+    const double ext = std::max(fabs((double)m->front), fabs((double)m->rear));
+    const double hw = m->half_width;
+    const double rc = sqrt(ext * ext + hw * hw) * (1.0 + 1e-3);
+    const double R = m->feature_set != NNP_FEAT_PAPER ? std::max(rc, (double)m->d_cap) : rc;
+    c.coll_r2 = round_up_f(rc * rc * (1.0 + 1e-5));
+    c.cull_r2 = round_up_f(R * R * (1.0 + 1e-5));
+    const double dmax = m->delta_max;
+    if (dmax < 0.5 * M_PI - 1e-3) {
+        const double tb = (double)m->lr / ((double)m->lf + m->lr) * tan(dmax) * (1.0 + 1e-6);
+        c.step_scale = round_up_f(m->dt * sqrt(1.0 + tb * tb) * (1.0 + 1e-5));
+    }
+    return c;
 }
 
 DevModel derive(const nnp_model *m)
@@ -910,11 +1276,61 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
     a.n_prop = p->n_prop;
     a.mu = p->n_prop > 0 ? p->prop_mu : nullptr;
     a.log_sigma = p->n_prop > 0 ? p->prop_log_sigma : nullptr;
+    a.cull_r2 = h->cull.cull_r2;
+    a.coll_r2 = h->cull.coll_r2;
+    a.step_scale = h->cull.step_scale;
     return NNP_OK;
 }
 
-// Extrapolation-table entries of one problem, with the slack the LDS copies may read past it.
-size_t table_entries(const RolloutArgs &a) { return (size_t)(a.T + 1) * a.P2 + CHUNK; }
+// Device tables of one problem, in float4 entries: the extrapolated pairs and the group boxes,
+// each with the slack the LDS copies may read past its end, then the spatial order of the points
+// (P <= SORT_MAX only).
+struct TableLayout {
+    size_t ext, bb, perm, disp;
+};
+
+TableLayout table_layout(const RolloutArgs &a)
+{
+    TableLayout l;
+    l.ext = (size_t)(a.T + 1) * a.P2 + CHUNK;
+    l.bb = (size_t)(a.T + 1) * (a.P2 / GROUP_PAIRS) + CHUNK;
+    l.perm = (a.P > 0 && a.P <= SORT_MAX) ? ((size_t)a.P + 3) / 4 : 0;
+    l.disp = 1;
+    return l;
+}
+
+size_t table_entries(const RolloutArgs &a)
+{
+    const TableLayout l = table_layout(a);
+    return l.ext + l.bb + l.perm + l.disp;
+}
+
+// Point a problem's table pointers into a region of table_entries(a) entries at `base`.
+void place_tables(RolloutArgs &a, float4 *base)
+{
+    const TableLayout l = table_layout(a);
+    a.ext = base;
+    a.bb = base + l.ext;
+    a.perm = l.perm ? reinterpret_cast<uint32_t *>(base + l.ext + l.bb) : nullptr;
+    a.disp = reinterpret_cast<float *>(base + l.ext + l.bb + l.perm);
+}
+
+// The spatial order and the points' displacement bound, then the extrapolation table and its
+// group boxes, of one problem whose tables are placed; also resets its argmin key.
+hipError_t launch_tables(const RolloutArgs &a, hipStream_t s)
+{
+    if (a.P > 0) {
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(ORDER_BLOCK), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const long long n = (long long)(a.T + 1) * a.P2;
+    const unsigned grid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
+    hipLaunchKernelGGL(extrapolate_kernel, dim3(grid), dim3(BLOCK), 0, s, a.obst, a.perm, a.P,
+                       a.P2, a.T, a.m.dt, const_cast<float4 *>(a.ext), const_cast<float4 *>(a.bb),
+                       a.best_key);
+    return hipGetLastError();
+}
 
 // Device workspace held by the handle's grown buffers.
 uint64_t workspace_bytes(const nnp_handle *h)
@@ -954,14 +1370,9 @@ int prepare(nnp_handle *h, const nnp_problem *p, RolloutArgs &a, hipStream_t s)
     rc = grow(h, reinterpret_cast<void **>(&h->d_ext), &h->ext_bytes,
               table_entries(a) * sizeof(float4), s, "extrapolation table");
     if (rc) return rc;
-    a.ext = h->d_ext;
+    place_tables(a, h->d_ext);
     a.best_key = h->d_key;
-    const long long n = (long long)(p->T + 1) * a.P2;
-    const unsigned grid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
-    hipLaunchKernelGGL(extrapolate_kernel, dim3(grid), dim3(BLOCK), 0, s,
-                       reinterpret_cast<const float4 *>(p->obst), p->P, a.P2, p->T, h->dm.dt,
-                       h->d_ext, h->d_key);
-    e = hipGetLastError();
+    e = launch_tables(a, s);
     if (e != hipSuccess) return hip_fail(h, e, "extrapolate_kernel launch");
     return NNP_OK;
 }
@@ -1023,6 +1434,7 @@ int nnp_create(nnp_handle **out, const nnp_model *m, int device)
     if (!h) return fail(nullptr, NNP_ENOMEM, "host allocation failed");
     h->model = *m;
     h->dm = derive(m);
+    h->cull = cull_consts(m);
     h->var = find_variant(m, m->lanes_per_sample, m->block_threads, m->tile_pairs);
     h->device = device;
     h->err.reserve(1024);
@@ -1136,14 +1548,9 @@ int nnp_plan_noalloc(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *h
     unsigned long long *key = reinterpret_cast<unsigned long long *>(base);
     float4 *ext = reinterpret_cast<float4 *>(base + NOALLOC_KEY_BYTES);
     a.best_key = key;
-    a.ext = ext;
-    // the table and the key reset (every call starts the argmin from ~0)
-    const long long n = (long long)(p->T + 1) * a.P2;
-    const unsigned tgrid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
-    hipLaunchKernelGGL(extrapolate_kernel, dim3(tgrid), dim3(BLOCK), 0, s,
-                       reinterpret_cast<const float4 *>(p->obst), p->P, a.P2, p->T, h->dm.dt, ext,
-                       key);
-    e = hipGetLastError();
+    place_tables(a, ext);
+    // the tables and the key reset (every call starts the argmin from ~0)
+    e = launch_tables(a, s);
     if (e != hipSuccess)
         return fail_fixed(h, NNP_EDEVICE, "extrapolate_kernel launch", hipGetErrorString(e));
     // the rollout without per-sample records, then the winner re-simulated
@@ -1235,7 +1642,7 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
                                                          (sizeof(RolloutArgs) + sizeof(ReplayOut)));
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
-        args[i].ext = static_cast<float4 *>(h->d_bext) + off;
+        place_tables(args[i], static_cast<float4 *>(h->d_bext) + off);
         off += table_entries(args[i]);
         args[i].best_key = static_cast<unsigned long long *>(h->d_bkeys) + i;
         h_args[i] = args[i];
@@ -1250,6 +1657,9 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
         e = hipEventRecord(h->meta_copied, s);
         if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
     }
+    hipLaunchKernelGGL(order_batch_kernel, dim3(count), dim3(ORDER_BLOCK), 0, s, d_args);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "order_batch_kernel launch");
     hipLaunchKernelGGL(extrapolate_batch_kernel, dim3(64, count), dim3(BLOCK), 0, s, d_args);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "extrapolate_batch_kernel launch");
@@ -1278,6 +1688,7 @@ int nnp_rollout(nnp_handle *h, const nnp_problem *p, const float *theta, nnp_rol
     a.collided = o->collided;
     a.first = o->first_collision;
     a.min_margin = o->min_margin;
+    if (o->min_margin) a.cull_r2 = INFINITY;   // the margin is a minimum over every point
     a.traj = o->traj;
     a.controls = o->controls;
     rc = launch_rollout(h, a, MODE_OUT, s);

@@ -38,7 +38,7 @@ class nnp_model(C.Structure):
         ("eps_xi", C.c_float), ("eps_eta", C.c_float), ("eps_phi", C.c_float),
         ("eps_v", C.c_float), ("lanes_per_sample", C.c_int32),
         ("goal_heading_weight", C.c_float), ("goal_speed_weight", C.c_float),
-        ("block_threads", C.c_int32), ("tile_pairs", C.c_int32),
+        ("block_threads", C.c_int32), ("tile_pairs", C.c_int32), ("all_points", C.c_int32),
     ]
 
 
@@ -190,7 +190,7 @@ def nnp_version() -> str:
 # Marshalling helpers
 # --------------------------------------------------------------------------------------------
 def make_model(p: dict, lanes_per_sample: int = 0, block_threads: int = 0,
-               tile_pairs: int = 0) -> nnp_model:
+               tile_pairs: int = 0, all_points: bool = False) -> nnp_model:
     m = nnp_model()
     for k in ("dt", "lf", "lr", "front", "rear", "half_width", "delta_max", "delta_rate_max",
               "u_min", "u_max", "v_min", "v_max", "norm_xi", "norm_eta", "norm_phi", "norm_v",
@@ -204,6 +204,7 @@ def make_model(p: dict, lanes_per_sample: int = 0, block_threads: int = 0,
     m.lanes_per_sample = int(lanes_per_sample)
     m.block_threads = int(block_threads)
     m.tile_pairs = int(tile_pairs)
+    m.all_points = int(bool(all_points))
     m.goal_heading_weight = float(np.float32(p.get("goal_heading_weight", 0.0)))
     m.goal_speed_weight = float(np.float32(p.get("goal_speed_weight", 0.0)))
     return m
@@ -225,11 +226,11 @@ class Planner:
     """A planner handle for one model on one device, fed with torch tensors."""
 
     def __init__(self, preset: dict, device: int = 0, lanes_per_sample: int = 0,
-                 block_threads: int = 0, tile_pairs: int = 0):
+                 block_threads: int = 0, tile_pairs: int = 0, all_points: bool = False):
         import torch
         self.torch = torch
         self.preset = dict(preset)
-        self.model = make_model(preset, lanes_per_sample, block_threads, tile_pairs)
+        self.model = make_model(preset, lanes_per_sample, block_threads, tile_pairs, all_points)
         self.device = device
         rc, self.h = nnp_create(self.model, device)
         if rc != NNP_OK:
@@ -409,14 +410,18 @@ class Planner:
         return outs
 
     def rollout(self, scene, N: int, seed: int = 0, inst: int = 0, theta=None,
-                want_traj: bool = True, want_controls: bool = True, proposal=None) -> dict:
+                want_traj: bool = True, want_controls: bool = True, proposal=None,
+                want_margin: bool = True) -> dict:
+        """Per-sample outputs of nnp_rollout. The minimum margin is a minimum over every point,
+        so requesting it (want_margin) makes the call test every point."""
         torch, d = self.torch, self._dev()
         pr, keep = self.problem(scene, N, seed, inst, proposal=proposal)
         T = scene.T
         out = dict(cost=torch.empty(N, dtype=torch.float32, device=d),
                    collided=torch.empty(N, dtype=torch.int32, device=d),
-                   first_collision=torch.empty(N, dtype=torch.int32, device=d),
-                   min_margin=torch.empty(N, dtype=torch.float32, device=d))
+                   first_collision=torch.empty(N, dtype=torch.int32, device=d))
+        if want_margin:
+            out["min_margin"] = torch.empty(N, dtype=torch.float32, device=d)
         if want_traj:
             out["traj"] = torch.empty(N, T + 1, 4, dtype=torch.float32, device=d)
         if want_controls:
