@@ -259,6 +259,17 @@ const char *nnp_last_error(const nnp_handle *h);
 int nnp_set_timing(nnp_handle *h, int enable);
 int nnp_kernel_time(nnp_handle *h, double *ms, int64_t *launches, int reset);
 
+/* Work counter of the obstacle pass's group skipping (nnp_model.all_points = 0): when enabled,
+ * every rollout kernel launched through the handle (nnp_plan, nnp_plan_noalloc, nnp_plan_batch,
+ * nnp_rollout) adds, per wavefront and step (and tile), the number of point groups it tested and
+ * the number the step has; nnp_cull_stats synchronises the device and returns both sums since
+ * the last reset (their ratio is the share of the point tests actually executed). Enabling
+ * allocates and clears a 16-byte device counter (synchronously; not under stream capture);
+ * disabling keeps it but stops the counting. Counting costs two device atomics per wavefront and
+ * tile. Returns NNP_OK, NNP_EINVAL (null handle) or NNP_ENOMEM / NNP_EDEVICE. */
+int nnp_set_cull_stats(nnp_handle *h, int enable);
+int nnp_cull_stats(nnp_handle *h, uint64_t *tested, uint64_t *total, int reset);
+
 /* Library version string. */
 const char *nnp_version(void);
 

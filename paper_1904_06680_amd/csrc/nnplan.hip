@@ -74,6 +74,7 @@ struct RolloutArgs {
     const float4 *bb;                // [T+1][P2 / GROUP_PAIRS] group boxes (xmin, ymin, xmax, ymax)
     uint32_t *perm;                  // [P] spatial order of the points, or null (caller's order)
     float *disp;                     // [1] bound on a point's move between two steps (order_kernel)
+    unsigned long long *stats;       // [2] tested / all point groups per wavefront-tile, or null
     float cull_r2;                   // squared cull radius; +INFINITY tests every group
     float coll_r2;                   // squared collision radius (the rectangle's corner distance)
     float step_scale;                // bound on |z_{h+1} - z_h| (x, y) per unit of |v_h|
@@ -647,6 +648,10 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
                 const uint64_t need =
                     cull ? group_mask<K>(sh.bbuf[it & 1] + g0, ng, pose.x, pose.y, thr, q)
                          : (ng >= 64 ? ~0ull : (1ull << ng) - 1);
+                if (a.stats && (tid & 63) == 0) {
+                    atomicAdd(a.stats, (unsigned long long)__builtin_popcountll(need));
+                    atomicAdd(a.stats + 1, (unsigned long long)ng);
+                }
                 point_pass_groups<(K >= 16 ? 2 : 4), CENTRED, K>(
                     pose, pbuf[it & 1] + g0 * GROUP_PAIRS + q, need, mm, md);
             }
@@ -1048,6 +1053,8 @@ struct nnp_handle {
     float4 *d_ext = nullptr;           // extrapolation table, group boxes, spatial order
     size_t ext_bytes = 0;
     CullConsts cull;                   // culling constants of the model (cull_consts)
+    unsigned long long *d_stats = nullptr;   // culling work counter (nnp_set_cull_stats)
+    bool stats = false;
     // per-sample records of nnp_plan (states and controls of every sample)
     void *d_rec = nullptr;
     size_t rec_bytes = 0;
@@ -1279,6 +1286,7 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
     a.cull_r2 = h->cull.cull_r2;
     a.coll_r2 = h->cull.coll_r2;
     a.step_scale = h->cull.step_scale;
+    a.stats = h->stats ? h->d_stats : nullptr;
     return NNP_OK;
 }
 
@@ -1465,6 +1473,7 @@ void nnp_destroy(nnp_handle *h)
     if (h->d_ext) hipFree(h->d_ext);
     if (h->d_rec) hipFree(h->d_rec);
     if (h->d_key) hipFree(h->d_key);
+    if (h->d_stats) hipFree(h->d_stats);
     if (h->d_bext) hipFree(h->d_bext);
     if (h->d_bkeys) hipFree(h->d_bkeys);
     if (h->d_bmeta) hipFree(h->d_bmeta);
@@ -1730,6 +1739,39 @@ int nnp_set_timing(nnp_handle *h, int enable)
 {
     if (!h) return NNP_EINVAL;
     h->timing = enable != 0;
+    return NNP_OK;
+}
+
+int nnp_set_cull_stats(nnp_handle *h, int enable)
+{
+    if (!h) return NNP_EINVAL;
+    if (enable) {
+        hipError_t e = hipSetDevice(h->device);
+        if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+        if (!h->d_stats && hipMalloc(&h->d_stats, 2 * sizeof(unsigned long long)) != hipSuccess) {
+            h->d_stats = nullptr;
+            return fail(h, NNP_ENOMEM, "hipMalloc of the culling counter failed");
+        }
+        e = hipMemset(h->d_stats, 0, 2 * sizeof(unsigned long long));
+        if (e != hipSuccess) return hip_fail(h, e, "hipMemset");
+    }
+    h->stats = enable != 0;
+    return NNP_OK;
+}
+
+int nnp_cull_stats(nnp_handle *h, uint64_t *tested, uint64_t *total, int reset)
+{
+    if (!h) return NNP_EINVAL;
+    unsigned long long v[2] = {0, 0};
+    if (h->d_stats) {
+        hipError_t e = hipSetDevice(h->device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(v, h->d_stats, sizeof v, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && reset) e = hipMemset(h->d_stats, 0, sizeof v);
+        if (e != hipSuccess) return hip_fail(h, e, "reading the culling counter");
+    }
+    if (tested) *tested = v[0];
+    if (total) *total = v[1];
     return NNP_OK;
 }
 

@@ -22,6 +22,7 @@ FEAT_PAPER, FEAT_SIX, FEAT_EIGHT = 0, 1, 2
 EXPORTED = ("nnp_create", "nnp_destroy", "nnp_n_theta", "nnp_plan", "nnp_plan_noalloc",
             "nnp_plan_batch", "nnp_rollout",
             "nnp_sample_theta", "nnp_sample_gauss", "nnp_last_error", "nnp_set_timing", "nnp_kernel_time",
+            "nnp_set_cull_stats", "nnp_cull_stats",
             "nnp_set_record_limit", "nnp_set_workspace_limit", "nnp_version")
 
 
@@ -100,6 +101,8 @@ def load_library(path: str = LIB):
                                        C.c_void_p]),
         "nnp_last_error": (C.c_char_p, [H]),
         "nnp_set_timing": (C.c_int, [H, C.c_int]),
+        "nnp_set_cull_stats": (C.c_int, [H, C.c_int]),
+        "nnp_cull_stats": (C.c_int, [H, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int]),
         "nnp_set_record_limit": (C.c_int, [H, C.c_uint64]),
         "nnp_set_workspace_limit": (C.c_int, [H, C.c_uint64]),
         "nnp_kernel_time": (C.c_int, [H, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
@@ -180,6 +183,16 @@ def nnp_kernel_time(h, reset: bool = False):
     ms, n = C.c_double(), C.c_int64()
     rc = load_library().nnp_kernel_time(h, C.byref(ms), C.byref(n), int(reset))
     return rc, ms.value, n.value
+
+
+def nnp_set_cull_stats(h, enable: bool) -> int:
+    return load_library().nnp_set_cull_stats(h, int(enable))
+
+
+def nnp_cull_stats(h, reset: bool = False):
+    tested, total = C.c_uint64(), C.c_uint64()
+    rc = load_library().nnp_cull_stats(h, C.byref(tested), C.byref(total), int(reset))
+    return rc, tested.value, total.value
 
 
 def nnp_version() -> str:
@@ -465,6 +478,16 @@ class Planner:
     def set_workspace_limit(self, nbytes: int):
         """Cap on the handle's grown device workspace; calls needing more raise (NNP_ENOMEM)."""
         _check(nnp_set_workspace_limit(self.h, nbytes), self.h)
+
+    def set_cull_stats(self, enable: bool = True):
+        """Count the point groups the obstacle pass tests (see cull_stats)."""
+        _check(nnp_set_cull_stats(self.h, enable), self.h)
+
+    def cull_stats(self, reset: bool = False):
+        """(tested, total) point groups over wavefront-steps since the last reset."""
+        rc, tested, total = nnp_cull_stats(self.h, reset)
+        _check(rc, self.h)
+        return tested, total
 
     def kernel_time(self, reset: bool = False):
         rc, ms, n = nnp_kernel_time(self.h, reset)

@@ -170,3 +170,30 @@ def test_batch_identical():
         assert_same(np_out(got[i]), np_out(ref[i]), ("batch", shapes[i]))
     cu.close()
     al.close()
+
+
+def test_work_counter():
+    """The counter of tested groups: every group counted once per wavefront and step, the tested
+    ones no more than all; with every point tested (all_points) they are equal. Counting does not
+    change the results."""
+    sc = scenes.scene_c1(4)
+    N = 8192
+    cu, al = pair(scenes.C1)
+    ref = np_out(cu.plan(sc, N, seed=1))
+    for pl in (cu, al):
+        pl.set_cull_stats(True)
+        out = np_out(pl.plan(sc, N, seed=1))
+        assert_same(out, ref, "counting")
+        tested, total = pl.cull_stats(reset=True)
+        waves = N * 8 // 64              # eight lanes per sample: 64 wavefronts per 512 samples
+        groups = -(-sc.P // 64)          # points padded to a multiple of 64: one group each
+        assert total == waves * (sc.T + 1) * groups, (total, waves, groups)
+        say(f"cull counter: {tested} of {total} groups tested ({tested / total:.3f})",
+            "all points" if pl is al else "")
+        if pl is al:
+            assert tested == total
+        else:
+            assert 0 < tested < total
+        assert pl.cull_stats() == (0, 0)
+    cu.close()
+    al.close()
