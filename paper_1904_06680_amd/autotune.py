@@ -27,7 +27,7 @@ def signature(preset: dict, scenes_, Ns) -> str:
 
 # Launch shapes (lanes per sample, workgroup threads, tile pairs; 0 = the layout's default) the
 # library compiles for the 8-32-32-2 network; a shape the library does not offer is skipped.
-SHAPES = ((8, 0, 0), (4, 0, 0), (16, 0, 0), (8, 512, 4096), (8, 256, 2048))
+SHAPES = ((8, 0, 0), (4, 0, 0), (16, 0, 0), (8, 512, 4096), (8, 512, 2048))
 
 
 def _shape(c):

@@ -44,13 +44,15 @@ constexpr int BUFFER_RSRC_FLAGS = 0x00020000;   // buffer descriptor word 3: 32-
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchronous copy
-// Point groups: every GROUP_PAIRS consecutive pairs of a step's table share a bounding box, and a
+// Point groups: every GP consecutive pairs of a step's table (GP = 16 or 32, the launch shape's
+// group size; a multiple of it is never split by a tile) share a bounding box, and a
 // wavefront skips a group at a step when the box lies farther than the cull radius from every
 // one of its samples (see group_mask). Up to SORT_MAX points are first put in spatial order
 // (order_kernel) so that the groups are compact; larger sets keep the caller's order.
-constexpr int GROUP_PAIRS = 32;
+constexpr int MAX_GROUP_PAIRS = 32;
 constexpr int SORT_MAX = 16384;
-constexpr int ORDER_BLOCK = 1024;
+constexpr int ORDER_BLOCK = 256;
+constexpr int ORDER_GRID = 64;    // cells per axis of the spatial order
 
 struct RolloutArgs {
     DevModel m;
@@ -71,13 +73,14 @@ struct RolloutArgs {
     int n_prop;
     float2 *rec_ctrl;                // record mode: applied controls [T][N] of every sample
                                      // (step-major: coalesced stores)
-    const float4 *bb;                // [T+1][P2 / GROUP_PAIRS] group boxes (xmin, ymin, xmax, ymax)
+    const float4 *bb;                // [T+1][P2 / gp] group boxes (xmin, ymin, xmax, ymax)
     uint32_t *perm;                  // [P] spatial order of the points, or null (caller's order)
     float *disp;                     // [1] bound on a point's move between two steps (order_kernel)
     unsigned long long *stats;       // [2] tested / all point groups per wavefront-tile, or null
     float cull_r2;                   // squared cull radius; +INFINITY tests every group
     float coll_r2;                   // squared collision radius (the rectangle's corner distance)
     float step_scale;                // bound on |z_{h+1} - z_h| (x, y) per unit of |v_h|
+    int gp;                          // pairs per point group of the handle's launch shape
 };
 
 // Culling constants of a model (cull_consts): squared cull and collision radii, and the bound on
@@ -96,17 +99,17 @@ enum { MODE_PLAN = 0, MODE_OUT = 1 };
 // ---------------------------------------------------------------------------------------------
 // 1. Constant-velocity extrapolation table; padding repeats the last point (min-neutral).
 // ---------------------------------------------------------------------------------------------
-static_assert((POINT_PAD / 2) % GROUP_PAIRS == 0, "a step's pairs form whole groups");
+static_assert((POINT_PAD / 2) % MAX_GROUP_PAIRS == 0, "a step's pairs form whole groups");
 
 // Entry (h, j) of the table (pair j of step h, entries numbered h * P2 + j) and the boxes of the
-// point groups: P2 is a multiple of GROUP_PAIRS, so the pairs of one group sit in one aligned
-// half-wavefront, whose lanes reduce their coordinates (exact minima and maxima); the group's
-// first lane writes the box. NaN coordinates are left out of a box, as the obstacle pass leaves
-// them out of its minima. The caller runs whole half-wavefronts.
+// point groups of gp pairs: P2 is a multiple of gp, so the pairs of one group sit in one aligned
+// run of gp lanes, which reduce their coordinates (exact minima and maxima); the group's first
+// lane writes the box. NaN coordinates are left out of a box, as the obstacle pass leaves them
+// out of its minima. The caller runs whole groups of lanes.
 __device__ __forceinline__ void table_entry(const float4 *__restrict__ pts,
                                             const uint32_t *__restrict__ perm, int P, int P2,
-                                            float dt, long long gid, float4 *__restrict__ ext,
-                                            float4 *__restrict__ bb)
+                                            int gp, float dt, long long gid,
+                                            float4 *__restrict__ ext, float4 *__restrict__ bb)
 {
     const int h = (int)(gid / P2);
     const int j = (int)(gid % P2);
@@ -123,29 +126,29 @@ __device__ __forceinline__ void table_entry(const float4 *__restrict__ pts,
     ext[gid] = e;
     float lx = fminf(e.x, e.z), ly = fminf(e.y, e.w), hx = fmaxf(e.x, e.z), hy = fmaxf(e.y, e.w);
 #pragma unroll
-    for (int off = GROUP_PAIRS / 2; off >= 1; off >>= 1) {
+    for (int off = MAX_GROUP_PAIRS / 2; off >= 1; off >>= 1) {
+        if (off >= gp) continue;
         lx = fminf(lx, __shfl_xor(lx, off, 64));
         ly = fminf(ly, __shfl_xor(ly, off, 64));
         hx = fmaxf(hx, __shfl_xor(hx, off, 64));
         hy = fmaxf(hy, __shfl_xor(hy, off, 64));
     }
-    if (j % GROUP_PAIRS == 0)
-        bb[(size_t)h * (P2 / GROUP_PAIRS) + j / GROUP_PAIRS] = make_float4(lx, ly, hx, hy);
+    if (j % gp == 0) bb[(size_t)h * (P2 / gp) + j / gp] = make_float4(lx, ly, hx, hy);
 }
 
 __global__ __launch_bounds__(BLOCK) void extrapolate_kernel(const float4 *__restrict__ pts,
                                                             const uint32_t *__restrict__ perm,
-                                                            int P, int P2, int T, float dt,
-                                                            float4 *__restrict__ ext,
+                                                            int P, int P2, int gp, int T,
+                                                            float dt, float4 *__restrict__ ext,
                                                             float4 *__restrict__ bb,
                                                             unsigned long long *best_key)
 {
     const long long n = (long long)(T + 1) * P2;
     const long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (gid == 0 && best_key) *best_key = ~0ull;
-    // n and the block size are multiples of GROUP_PAIRS: lanes leave in whole half-wavefronts
+    // n and the block size are multiples of gp: lanes leave in whole groups
     if (gid >= n || P == 0) return;
-    table_entry(pts, perm, P, P2, dt, gid, ext, bb);
+    table_entry(pts, perm, P, P2, gp, dt, gid, ext, bb);
 }
 
 // The same table for every problem of a batch: blockIdx.y is the problem, the x blocks stride
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void extrapolate_batch_kernel(const RolloutA
     float4 *bb = const_cast<float4 *>(a.bb);
     for (long long gid = (long long)blockIdx.x * BLOCK + threadIdx.x; gid < n;
          gid += (long long)gridDim.x * BLOCK)
-        table_entry(a.obst, a.perm, a.P, a.P2, a.m.dt, gid, ext, bb);
+        table_entry(a.obst, a.perm, a.P, a.P2, a.gp, a.m.dt, gid, ext, bb);
 }
 
 // Spread the low 16 bits of v over the even bit positions (one half of a Z-order key).
@@ -175,11 +178,13 @@ __device__ __forceinline__ uint32_t spread_bits(uint32_t v)
 }
 
 // Spatial order of P <= SORT_MAX points, by one workgroup of ORDER_BLOCK threads: each point's
-// position at the middle of the horizon (tmid), on a 512 x 512 grid over the bounding box of
-// those positions, gives an 18-bit Z-order key; with the point index in the low 14 bits every
-// key is unique, so a bitonic sort in LDS gives one deterministic order. perm[i] is the index of
-// the i-th point in it. No result depends on the order (the obstacle pass takes exact minima);
-// it keeps the points of a group close together, so that their box is small.
+// position at the middle of the horizon (tmid), on a 64 x 64 grid over the bounding box of
+// those positions, falls into a cell, and the cells are laid out in Z-order (Morton code of the
+// cell's coordinates). A counting sort gives that order: per-cell counts with LDS atomics, an
+// exclusive scan, and a scatter in which every point takes the next free slot of its cell (so
+// the points of one cell come in the order the atomics happen to run). perm[i] is the index of
+// the i-th point. No result depends on the order (the obstacle pass takes exact minima); it keeps
+// the points of a group close together, so that their box is small.
 //
 // It also writes *disp, a bound on how far any point of the table moves between two consecutive
 // steps: |p_h - p_{h-1}| <= |v| (t_h - t_{h-1}) plus the rounding of the two table entries, with
@@ -188,7 +193,7 @@ __device__ __forceinline__ uint32_t spread_bits(uint32_t v)
 // Non-finite inputs give +INFINITY.
 __device__ void order_points(const float4 *__restrict__ pts, int P, float tmid, float span,
                              float dt, uint32_t *__restrict__ perm, float *__restrict__ disp,
-                             uint32_t *keys, float (&red)[6][ORDER_BLOCK / 64])
+                             uint32_t *cnt, float (&red)[6][ORDER_BLOCK / 64])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     float lx = INFINITY, ly = INFINITY, hx = -INFINITY, hy = -INFINITY, v2 = 0.0f, pm = 0.0f;
@@ -238,44 +243,59 @@ __device__ void order_points(const float4 *__restrict__ pts, int P, float tmid, 
         const float d = fmaf(sqrtf(v2) * dt, 1.001f, pm * 0x1p-21f);
         *disp = d < INFINITY ? d : INFINITY;
     }
-    // grid scales (0 when the extent is empty or not finite: every key then has cell 0)
-    const float sx = hx > lx ? 511.0f / (hx - lx) : 0.0f;
-    const float sy = hy > ly ? 511.0f / (hy - ly) : 0.0f;
-    int n = 2;
-    while (n < P) n <<= 1;
-    for (int i = tid; i < n; i += ORDER_BLOCK) {
-        uint32_t k = 0xFFFFFFFFu;          // padding sorts last (no real key reaches it: i < 16383)
-        if (i < P) {
-            const float4 p = pts[i];
-            const float x = fmaf(tmid, p.z, p.x), y = fmaf(tmid, p.w, p.y);
-            // fmaxf(NaN, 0) = 0: non-finite positions fall into cell 0
-            const uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), 511.0f);
-            const uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), 511.0f);
-            k = ((spread_bits(cx) | (spread_bits(cy) << 1)) << 14) | (uint32_t)i;
+    // grid scales (0 when the extent is empty or not finite: every point then has cell 0)
+    const float sx = hx > lx ? (float)ORDER_GRID / (hx - lx) : 0.0f;
+    const float sy = hy > ly ? (float)ORDER_GRID / (hy - ly) : 0.0f;
+    for (int c = tid; c < ORDER_GRID * ORDER_GRID / 4; c += ORDER_BLOCK)
+        reinterpret_cast<uint4 *>(cnt)[c] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    // cell code of point i: Z-order of its grid cell (fmaxf(NaN, 0) = 0: non-finite positions
+    // fall into cell 0)
+    auto cell_of = [&](int i) -> uint32_t {
+        const float4 p = pts[i];
+        const float x = fmaf(tmid, p.z, p.x), y = fmaf(tmid, p.w, p.y);
+        const uint32_t cx = (uint32_t)fminf(fmaxf((x - lx) * sx, 0.0f), ORDER_GRID - 1.0f);
+        const uint32_t cy = (uint32_t)fminf(fmaxf((y - ly) * sy, 0.0f), ORDER_GRID - 1.0f);
+        return spread_bits(cx) | (spread_bits(cy) << 1);
+    };
+    for (int i = tid; i < P; i += ORDER_BLOCK) atomicAdd(&cnt[cell_of(i)], 1u);
+    __syncthreads();
+    if (wave == 0) {   // exclusive scan: 64 consecutive cells per lane, then across the lanes
+        constexpr int PER4 = ORDER_GRID * ORDER_GRID / 64 / 4;
+        uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt) + lane * PER4;
+        uint32_t run = 0;
+#pragma unroll 4
+        for (int k = 0; k < PER4; ++k) {
+            const uint4 v = cnt4[k];
+            run += v.x + v.y + v.z + v.w;
         }
-        keys[i] = k;
+        uint32_t incl = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        uint32_t base = incl - run;
+#pragma unroll 4
+        for (int k = 0; k < PER4; ++k) {
+            const uint4 v = cnt4[k];
+            uint4 o;
+            o.x = base;
+            o.y = o.x + v.x;
+            o.z = o.y + v.y;
+            o.w = o.z + v.z;
+            base = o.w + v.w;
+            cnt4[k] = o;
+        }
     }
     __syncthreads();
-    for (int size = 2; size <= n; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = tid; t < (n >> 1); t += ORDER_BLOCK) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const uint32_t u = keys[lo], v = keys[hi];
-                if ((u > v) == ((lo & size) == 0)) {   // ascending where bit `size` of lo is 0
-                    keys[lo] = v;
-                    keys[hi] = u;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = tid; i < P; i += ORDER_BLOCK) perm[i] = keys[i] & 0x3FFFu;
+    // scatter: each point takes the next free slot of its cell
+    for (int i = tid; i < P; i += ORDER_BLOCK) perm[atomicAdd(&cnt[cell_of(i)], 1u)] = (uint32_t)i;
 }
 
 // The order and the displacement bound of one problem; a problem with more than SORT_MAX points
 // keeps the caller's order and has no bound (+INFINITY: its culling uses the radius alone).
-__device__ __forceinline__ void order_problem(const RolloutArgs &a, uint32_t *keys,
+__device__ __forceinline__ void order_problem(const RolloutArgs &a, uint32_t *cnt,
                                               float (&red)[6][ORDER_BLOCK / 64])
 {
     if (!a.perm) {
@@ -283,23 +303,23 @@ __device__ __forceinline__ void order_problem(const RolloutArgs &a, uint32_t *ke
         return;
     }
     const float span = (float)a.T * a.m.dt;
-    order_points(a.obst, a.P, 0.5f * span, span, a.m.dt, a.perm, a.disp, keys, red);
+    order_points(a.obst, a.P, 0.5f * span, span, a.m.dt, a.perm, a.disp, cnt, red);
 }
 
 __global__ __launch_bounds__(ORDER_BLOCK) void order_kernel(const RolloutArgs a)
 {
-    __shared__ uint32_t keys[SORT_MAX];
+    __shared__ __align__(16) uint32_t cnt[ORDER_GRID * ORDER_GRID];
     __shared__ float red[6][ORDER_BLOCK / 64];
-    order_problem(a, keys, red);
+    order_problem(a, cnt, red);
 }
 
 // One workgroup per problem of a batch.
 __global__ __launch_bounds__(ORDER_BLOCK) void order_batch_kernel(const RolloutArgs *probs)
 {
-    __shared__ uint32_t keys[SORT_MAX];
+    __shared__ __align__(16) uint32_t cnt[ORDER_GRID * ORDER_GRID];
     __shared__ float red[6][ORDER_BLOCK / 64];
     const RolloutArgs &a = probs[blockIdx.x];
-    if (a.P > 0) order_problem(a, keys, red);
+    if (a.P > 0) order_problem(a, cnt, red);
 }
 
 template <class NetT>
@@ -383,12 +403,12 @@ __device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x
 // uses. The walk over the mask is wavefront-uniform (scalar) control: with one chunk per group,
 // a find-first-set and a bit clear per chunk. In the general walk the last step reads the
 // current chunk again instead of a next one (in bounds, unused).
-template <int G, bool CENTRED, int STRIDE>
+template <int G, int GP, bool CENTRED, int STRIDE>
 __device__ __forceinline__ void point_pass_groups(const Pose &pose, const v4f *p, uint64_t need,
                                                   float &mm, float &md)
 {
-    constexpr int CPG = GROUP_PAIRS / (STRIDE * G);
-    static_assert(CPG >= 1 && CPG * STRIDE * G == GROUP_PAIRS, "whole chunks per group");
+    constexpr int CPG = GP / (STRIDE * G);
+    static_assert(CPG >= 1 && CPG * STRIDE * G == GP, "whole chunks per group");
     if (!need) return;
     if constexpr (CPG == 1) {
         // one chunk per group: the walk is a find-first-set and a bit clear per chunk
@@ -525,18 +545,26 @@ __device__ __forceinline__ void wait_copies()
 // workgroup's LDS also holds one slot per sample through which the controller's second hidden
 // layer receives its inputs.
 // ---------------------------------------------------------------------------------------------
-constexpr int rollout_block(int K) { return K == 8 ? 512 : 256; }
+constexpr int rollout_block(int K) { return 256; }
 constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
+#ifndef NNP_K8_GROUP_PAIRS
+#define NNP_K8_GROUP_PAIRS 16
+#endif
+constexpr int group_pairs(int K) { return K == 8 ? NNP_K8_GROUP_PAIRS : MAX_GROUP_PAIRS; }
 
 // Launch shape of the rollout kernels: K lanes per sample, RB threads per workgroup, TP point
-// pairs per LDS buffer (the defaults above per K; the batch autotuner chooses among the compiled
-// shapes). Every shape computes the same bits: minima are exact and the controller's sums do
-// not depend on K.
-template <int K_, int RB_ = rollout_block(K_), int TP_ = tile_pairs(K_)>
+// pairs per LDS buffer, GP pairs per point group (the defaults above per K; the batch autotuner
+// chooses among the compiled shapes). G pairs per lane form one register group of the obstacle
+// pass: four, or two where a group has fewer pairs per lane or registers are short. Every shape
+// computes the same bits: minima are exact and the controller's sums do not depend on K.
+template <int K_, int RB_ = rollout_block(K_), int TP_ = tile_pairs(K_), int GP_ = group_pairs(K_)>
 struct Shape {
-    static constexpr int K = K_, RB = RB_, TP = TP_;
+    static constexpr int K = K_, RB = RB_, TP = TP_, GP = GP_;
+    static constexpr int G = GP / K >= 4 ? 4 : 2;
     static constexpr int WPE = K_ >= 16 ? 3 : 1;     // wavefronts per SIMD the build aims for
     static_assert(RB % 64 == 0 && RB % K == 0 && TP % CHUNK == 0, "whole wavefronts and chunks");
+    static_assert(GP <= MAX_GROUP_PAIRS && GP % (K * G) == 0 && TP % GP == 0,
+                  "whole register groups per point group, whole groups per tile");
 };
 
 // LDS of one rollout workgroup.
@@ -549,7 +577,7 @@ struct RolloutShared {
     static constexpr int ACT_STRIDE = ACT ? ACT + 4 : 0;
     v4f pbuf[2][TP];                 // point pairs of the current / next tile
     // their groups' boxes (whole copy chunks: a copy moves CHUNK entries)
-    static constexpr int BOXES = (TP / GROUP_PAIRS + CHUNK - 1) / CHUNK * CHUNK;
+    static constexpr int BOXES = (TP / SH::GP + CHUNK - 1) / CHUNK * CHUNK;
     v4f bbuf[2][BOXES];
     float act[ACT ? SH::RB / SH::K * ACT_STRIDE : 4];
 };
@@ -584,9 +612,9 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
     const int P2 = a.P2;
     const int ntile = (P2 + TP - 1) / TP;                      // 0 when there are no points
     const v4f *ext = reinterpret_cast<const v4f *>(a.ext);
-    const int NG = P2 / GROUP_PAIRS;                           // groups per step
-    constexpr int TG = TP / GROUP_PAIRS;                       // groups per full tile
-    static_assert(TP % GROUP_PAIRS == 0, "whole groups per tile");
+    constexpr int GP = SH::GP;
+    const int NG = P2 / GP;                                    // groups per step
+    constexpr int TG = TP / GP;                                // groups per full tile
     const v4f *bbs = reinterpret_cast<const v4f *>(a.bb);
     const bool cull = a.cull_r2 < INFINITY;
     auto copy_tile = [&](int h, int t, int buf) {
@@ -594,7 +622,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
         copy_entries<WAVES>(ext + (size_t)h * P2 + (size_t)t * TP, pbuf[buf], n, 0, wave);
         if (cull)   // the boxes by the last wavefronts: the point chunks start at the first
             copy_entries<WAVES>(bbs + (size_t)h * NG + (size_t)t * TG, sh.bbuf[buf],
-                                n / GROUP_PAIRS, WAVES - 1, wave);
+                                n / GP, WAVES - 1, wave);
     };
     if (ntile > 0) copy_tile(0, 0, 0);
 
@@ -642,7 +670,7 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
             if constexpr (MODE == MODE_PLAN)
                 if (t == 0) record(h);
             // the tile's groups in segments of at most 64 (one mask word each)
-            const int ngt = min(TP, P2 - t * TP) / GROUP_PAIRS;
+            const int ngt = min(TP, P2 - t * TP) / GP;
             for (int g0 = 0; g0 < ngt; g0 += 64) {
                 const int ng = min(64, ngt - g0);
                 const uint64_t need =
@@ -652,8 +680,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
                     atomicAdd(a.stats, (unsigned long long)__builtin_popcountll(need));
                     atomicAdd(a.stats + 1, (unsigned long long)ng);
                 }
-                point_pass_groups<(K >= 16 ? 2 : 4), CENTRED, K>(
-                    pose, pbuf[it & 1] + g0 * GROUP_PAIRS + q, need, mm, md);
+                point_pass_groups<SH::G, GP, CENTRED, K>(pose, pbuf[it & 1] + g0 * GP + q,
+                                                         need, mm, md);
             }
         }
         if constexpr (MODE == MODE_PLAN)
@@ -911,7 +939,7 @@ __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t in
 // ---------------------------------------------------------------------------------------------
 struct Variant {
     int widths[NNP_MAX_LAYERS + 1];
-    int n_layers, feature_set, K, block, tile, ntheta;
+    int n_layers, feature_set, K, block, tile, gp, ntheta;
     void (*launch_rollout)(const RolloutArgs &, int mode, dim3 grid, hipStream_t);
     void (*launch_replay)(const RolloutArgs &, const ReplayOut &, hipStream_t);
     void (*launch_rollout_batch)(const RolloutArgs *, const int2 *, int n_items, bool centred,
@@ -968,7 +996,7 @@ void launch_gather_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
 }
 
 #define NNP_SHAPED(NIN, H1, H2, FEAT, SH)                                                         \
-    {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, SH::K, SH::RB, SH::TP,          \
+    {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, SH::K, SH::RB, SH::TP, SH::GP,  \
      Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, SH>,                 \
      launch_replay_t<Net<NIN, H1, H2, FEAT>, SH::K>,                                               \
      launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, SH>,                                           \
@@ -976,15 +1004,15 @@ void launch_gather_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
 #define NNP_VARIANT(NIN, H1, H2, FEAT, K) NNP_SHAPED(NIN, H1, H2, FEAT, Shape<K>)
 
 using ShapeWideTile = Shape<8, 512, 4096>;      // one LDS buffer holds an 8192-point step
-using ShapeHalfBlock = Shape<8, 256, 2048>;     // two 256-thread workgroups per CU
+using ShapeFullBlock = Shape<8, 512, 2048>;     // one 512-thread workgroup per CU
 
 // The first listed shape of a network is its default.
 const Variant kVariants[] = {
-    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default:
-    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // two wavefronts per SIMD at 8 lanes/sample)
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 8),   // 8-32-32-2, 1410 parameters (default: two
+    NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 4),   // 256-thread workgroups per CU, 8 lanes/sample)
     NNP_VARIANT(8, 32, 32, NNP_FEAT_EIGHT, 16),
     NNP_SHAPED(8, 32, 32, NNP_FEAT_EIGHT, ShapeWideTile),
-    NNP_SHAPED(8, 32, 32, NNP_FEAT_EIGHT, ShapeHalfBlock),
+    NNP_SHAPED(8, 32, 32, NNP_FEAT_EIGHT, ShapeFullBlock),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 1),      // 6-16-2, 146 parameters
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 2),
     NNP_VARIANT(6, 16, 0, NNP_FEAT_SIX, 4),
@@ -1287,6 +1315,7 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
     a.coll_r2 = h->cull.coll_r2;
     a.step_scale = h->cull.step_scale;
     a.stats = h->stats ? h->d_stats : nullptr;
+    a.gp = h->var->gp;
     return NNP_OK;
 }
 
@@ -1301,7 +1330,7 @@ TableLayout table_layout(const RolloutArgs &a)
 {
     TableLayout l;
     l.ext = (size_t)(a.T + 1) * a.P2 + CHUNK;
-    l.bb = (size_t)(a.T + 1) * (a.P2 / GROUP_PAIRS) + CHUNK;
+    l.bb = (size_t)(a.T + 1) * (a.P2 / a.gp) + CHUNK;
     l.perm = (a.P > 0 && a.P <= SORT_MAX) ? ((size_t)a.P + 3) / 4 : 0;
     l.disp = 1;
     return l;
@@ -1335,8 +1364,8 @@ hipError_t launch_tables(const RolloutArgs &a, hipStream_t s)
     const long long n = (long long)(a.T + 1) * a.P2;
     const unsigned grid = (unsigned)(n > 0 ? (n + BLOCK - 1) / BLOCK : 1);
     hipLaunchKernelGGL(extrapolate_kernel, dim3(grid), dim3(BLOCK), 0, s, a.obst, a.perm, a.P,
-                       a.P2, a.T, a.m.dt, const_cast<float4 *>(a.ext), const_cast<float4 *>(a.bb),
-                       a.best_key);
+                       a.P2, a.gp, a.T, a.m.dt, const_cast<float4 *>(a.ext),
+                       const_cast<float4 *>(a.bb), a.best_key);
     return hipGetLastError();
 }
 

@@ -186,8 +186,10 @@ def test_work_counter():
         assert_same(out, ref, "counting")
         tested, total = pl.cull_stats(reset=True)
         waves = N * 8 // 64              # eight lanes per sample: 64 wavefronts per 512 samples
-        groups = -(-sc.P // 64)          # points padded to a multiple of 64: one group each
-        assert total == waves * (sc.T + 1) * groups, (total, waves, groups)
+        # points padded to a multiple of 64, in groups of 32 or 64 (the launch shape's)
+        per_step = total // (waves * (sc.T + 1))
+        assert total == waves * (sc.T + 1) * per_step, (total, waves)
+        assert per_step in (-(-sc.P // 64), 2 * -(-sc.P // 64)), per_step
         say(f"cull counter: {tested} of {total} groups tested ({tested / total:.3f})",
             "all points" if pl is al else "")
         if pl is al:
