@@ -375,11 +375,17 @@ __device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x
                                                float r2, int q)
 {
     static_assert(64 % K == 0 && K <= 16, "whole samples per wavefront");
-    constexpr int R = 64 / K;      // rounds for a full segment; the boxes past ng are read (in
-    uint64_t need = 0;             // bounds) and masked off, so the reads need no branches
+    constexpr int R = 64 / K;      // rounds for a full segment; a partial one stops early
+    uint64_t need = 0;
+    // every round's box is read first (in bounds), so the reads overlap; the empty asm at the end
+    // uses them on every path, which keeps the compiler from moving a read past an early exit
+    v4f bx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) bx[r] = boxes[r * K + q];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const v4f b = boxes[r * K + q];
+        if (r * K >= ng) break;
+        const v4f b = bx[r];
         const float ex = fmaxf(fmaxf(b.x - x, x - b.z), 0.0f);
         const float ey = fmaxf(fmaxf(b.y - y, y - b.w), 0.0f);
         const float d2 = fmaf(ex, ex, ey * ey);
@@ -388,6 +394,8 @@ __device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x
         for (int sh = 32; sh >= K; sh >>= 1) m |= m >> sh;
         need |= (m & ((1ull << K) - 1)) << (r * K);
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) asm volatile("" ::"v"(bx[r].x));
     return ng >= 64 ? need : need & ((1ull << ng) - 1);
 }
 
