@@ -266,7 +266,7 @@ int nnp_kernel_time(nnp_handle *h, double *ms, int64_t *launches, int reset);
  * the last reset (their ratio is the share of the point tests actually executed). Enabling
  * allocates and clears a 16-byte device counter (synchronously; not under stream capture);
  * disabling keeps it but stops the counting. Counting costs two device atomics per wavefront and
- * tile. Returns NNP_OK, NNP_EINVAL (null handle) or NNP_ENOMEM / NNP_EDEVICE. */
+ * launch. Returns NNP_OK, NNP_EINVAL (null handle) or NNP_ENOMEM / NNP_EDEVICE. */
 int nnp_set_cull_stats(nnp_handle *h, int enable);
 int nnp_cull_stats(nnp_handle *h, uint64_t *tested, uint64_t *total, int reset);
 

@@ -662,6 +662,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
     // points' squared distances (a few float ulps each).
     const float disp = cull ? *a.disp : INFINITY;
     float bnd = INFINITY;
+    // work counter of the wavefront (wavefront-uniform), added to a.stats once at the end
+    unsigned long long n_tested = 0, n_groups = 0;
 
     int it = 0;
     for (int h = 0; h <= a.T; ++h) {
@@ -684,10 +686,8 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
                 const uint64_t need =
                     cull ? group_mask<K>(sh.bbuf[it & 1] + g0, ng, pose.x, pose.y, thr, q)
                          : (ng >= 64 ? ~0ull : (1ull << ng) - 1);
-                if (a.stats && (tid & 63) == 0) {
-                    atomicAdd(a.stats, (unsigned long long)__builtin_popcountll(need));
-                    atomicAdd(a.stats + 1, (unsigned long long)ng);
-                }
+                n_tested += (unsigned long long)__builtin_popcountll(need);
+                n_groups += (unsigned long long)ng;
                 point_pass_groups<SH::G, GP, CENTRED, K>(pose, pbuf[it & 1] + g0 * GP + q,
                                                          need, mm, md);
             }
@@ -722,6 +722,10 @@ __device__ __forceinline__ void rollout_tile(const RolloutArgs &a, int tile,
         }
     }
 
+    if (a.stats && (tid & 63) == 0) {
+        atomicAdd(a.stats, n_tested);
+        atomicAdd(a.stats + 1, n_groups);
+    }
     const float J = sim.cost(a.m, a.goal);
     if constexpr (MODE == MODE_PLAN) {
         unsigned long long key = ~0ull;
