@@ -1,19 +1,24 @@
 // nnplan: kernels and C-ABI of the MI355X rollout planner (declarations in include/nnplan.h).
 //
-// One planning call (Step 5 of Alg. 1, Sect. II-E) is three launches on the caller's stream:
-//   1. extrapolate_kernel  obstacle points at every step h = 0..T under constant velocity
-//                          (Sect. II-E items (ii)-(iv)) into a [T+1][P16] table of (x, y); it
-//                          also resets the argmin key.
-//   2. rollout_kernel      every sample rolled over the horizon: Philox parameters in
-//                          registers, per step a pass over all points (eq. (2) and the nearest
-//                          distance) from LDS buffers filled by asynchronous copies, features
-//                          (eq. (3)), MLP (eq. (4)), model (Sect. II-F) and the cost; a u64
-//                          (cost bits, index) atomicMin selects the best sample, lowest index on
-//                          ties. When the handle's record limit allows, every sample's states and
+// One planning call (Step 5 of Alg. 1, Sect. II-E) is four launches on the caller's stream:
+//   1. order_kernel        a spatial order of the obstacle points (grid cells in Z-order) and a
+//                          bound on how far any point moves between two steps.
+//   2. extrapolate_kernel  obstacle points at every step h = 0..T under constant velocity
+//                          (Sect. II-E items (ii)-(iv)) into a [T+1][P64/2] table of point pairs
+//                          in that order, with the bounding box of every group of consecutive
+//                          pairs; it also resets the argmin key.
+//   3. rollout_kernel      every sample rolled over the horizon: Philox parameters in
+//                          registers, per step a pass over the points (eq. (2) and the nearest
+//                          distance) from LDS buffers filled by asynchronous copies, skipping the
+//                          groups that cannot change any minimum of the wavefront's samples,
+//                          features (eq. (3)), MLP (eq. (4)), model (Sect. II-F) and the cost; a
+//                          u64 (cost bits, index) atomicMin selects the best sample, lowest index
+//                          on ties. When the handle's record limit allows, every sample's applied
 //                          controls are also stored (step-major, coalesced).
-//   3. gather_kernel       copies the winner's records and regenerates theta*; or, without
-//      / replay_kernel     records, one workgroup re-simulates the winner with the same device
-//                          functions (points split over 256 lanes). Both give the same bits.
+//   4. gather_kernel       re-integrates the winner's states from its recorded controls and
+//      / replay_kernel     regenerates theta*; or, without records, one workgroup re-simulates
+//                          the winner with the same device functions (points split over 256
+//                          lanes). Both give the same bits.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
