@@ -340,16 +340,18 @@ def bench_proposal(pl):
 def bench_served(pl, prop) -> dict:
     """Closed loop served: 64 vehicles (waypoint missions and reverse parking) x 200 steps, each
     plan 8192 proposal + 8192 uniform samples over T = 50, with the served preset's cost (terminal
-    heading and speed terms) and plan-based waypoint switching."""
+    heading and speed terms; the parking vehicles with their own weights) and plan-based waypoint
+    switching."""
     from paper_1904_06680_amd import serve
     from paper_1904_06680_amd.scenes import C4
-    vs, kinds = serve.c4_vehicles(64, device=pl._dev())
+    vs, kinds = serve.c4_vehicles(64, device=pl._dev(), goal_weights=serve.SERVED_GOAL_WEIGHTS)
     p4 = serve.tuned_planner(C4, vs, 50, 16384, device=pl.device)
     shape = [p4.model.lanes_per_sample, p4.model.block_threads, p4.model.tile_pairs]
     r = serve.run(p4, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
     p4.close()
     return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50, "
-                        "cost with terminal heading/speed terms, plan-based waypoint switching",
+                        "cost with terminal heading/speed terms (3, 0.5; parking 2, 0.5), "
+                        "plan-based waypoint switching",
             "latency_ms_p50": round(r["latency_ms"]["p50"], 3),
             "latency_ms_p99": round(r["latency_ms"]["p99"], 3),
             "rollout_steps_per_s": r["rollout_steps_per_s"],

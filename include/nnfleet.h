@@ -55,6 +55,9 @@ typedef struct nnp_vehicle_spec {
     int32_t n_waypoints;       /* >= 1; the mission is complete when the last one is reached   */
     const float *obst;         /* device [P][4] obstacle points (x, y, vx, vy) at t = 0; copied */
     int32_t P;                 /* 0..NNP_MAX_P                                                 */
+    int32_t own_goal_weights;  /* 1: this vehicle's plans weigh the goal's heading and speed    */
+    float goal_heading_weight; /* with these (nnp_problem's fields of the same names); 0: the   */
+    float goal_speed_weight;   /* planner model's                                              */
 } nnp_vehicle_spec;
 
 /* Per-vehicle status after a step (host copy). */

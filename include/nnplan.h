@@ -112,6 +112,12 @@ typedef struct nnp_problem {
                               /* uniform draws 0..N-n_prop-1 of stream 0. 0 = plain sampler.     */
     const float *prop_mu;        /* device [n_theta] proposal mean (may be NULL if n_prop = 0)   */
     const float *prop_log_sigma; /* device [n_theta] proposal log standard deviation             */
+    int32_t own_goal_weights;    /* 1: this problem's cost takes the two weights below instead   */
+                                 /* of the model's goal_heading_weight / goal_speed_weight       */
+                                 /* (finite, >= 0); 0: the model's (missions of different kinds  */
+                                 /* in one batch may weigh the goal's heading and speed apart)   */
+    float goal_heading_weight;
+    float goal_speed_weight;
 } nnp_problem;
 
 /* Outputs of nnp_plan: caller-owned device buffers; any member may be NULL to skip it. */

@@ -96,6 +96,7 @@ struct nnp_fleet {
     std::vector<std::vector<float>> wps;
     std::vector<long long> obst_off;
     std::vector<int> obst_n;
+    std::vector<nnp_vehicle_spec> spec;   // the specs as given (pointers not used after create)
     // device
     float4 *d_obst = nullptr;
     long long n_points = 0;
@@ -164,11 +165,17 @@ int nnp_fleet_create(nnp_fleet **out, nnp_handle *planner, nnp_proposal *proposa
     f->wps.resize((size_t)n);
     f->obst_off.resize((size_t)n);
     f->obst_n.resize((size_t)n);
+    f->spec.assign(veh, veh + n);
     long long total = 0;
     for (int i = 0; i < n; ++i) {
         const nnp_vehicle_spec &v = veh[i];
+        const bool weights_ok =
+            v.own_goal_weights == 0 ||
+            (v.own_goal_weights == 1 && v.goal_heading_weight >= 0.0f &&
+             v.goal_speed_weight >= 0.0f && isfinite(v.goal_heading_weight) &&
+             isfinite(v.goal_speed_weight));
         if (v.n_waypoints < 1 || !v.waypoints || v.P < 0 || v.P > NNP_MAX_P ||
-            (v.P > 0 && !v.obst)) {
+            (v.P > 0 && !v.obst) || !weights_ok) {
             delete f;
             return ffail(nullptr, NNP_EINVAL, "vehicle " + std::to_string(i) + ": bad spec");
         }
@@ -261,6 +268,9 @@ int nnp_fleet_step(nnp_fleet *f, void *hip_stream, double *latency_ms, int32_t *
         p.inst = (uint32_t)f->tick;
         p.seed = c.seed + (uint64_t)i;      // one Philox key per vehicle
         p.warm_theta = (c.warm_start && v.steps > 0) ? warm_in + (size_t)i * nt : nullptr;
+        p.own_goal_weights = f->spec[(size_t)i].own_goal_weights;
+        p.goal_heading_weight = f->spec[(size_t)i].goal_heading_weight;
+        p.goal_speed_weight = f->spec[(size_t)i].goal_speed_weight;
         if (f->prop) {
             p.n_prop = c.n_prop;
             p.prop_mu = f->d_mu + (size_t)j * nt;

@@ -1293,6 +1293,11 @@ int check_problem(nnp_handle *h, const nnp_problem *p)
     if (p->n_prop < 0 || p->n_prop > p->N) return fail(h, NNP_EINVAL, "n_prop must be in [0, N]");
     if (p->n_prop > 0 && (!p->prop_mu || !p->prop_log_sigma))
         return fail(h, NNP_EINVAL, "prop_mu / prop_log_sigma are null with n_prop > 0");
+    if (p->own_goal_weights != 0 && p->own_goal_weights != 1)
+        return fail(h, NNP_EINVAL, "own_goal_weights must be 0 or 1");
+    if (p->own_goal_weights && !(p->goal_heading_weight >= 0.0f && finite_f(p->goal_heading_weight) &&
+                                 p->goal_speed_weight >= 0.0f && finite_f(p->goal_speed_weight)))
+        return fail(h, NNP_EINVAL, "a problem's goal weights must be finite and >= 0");
     return NNP_OK;
 }
 
@@ -1303,6 +1308,10 @@ int fill_args(nnp_handle *h, const nnp_problem *p, RolloutArgs &a)
     if (rc) return rc;
     memset(&a, 0, sizeof a);
     a.m = h->dm;
+    if (p->own_goal_weights) {
+        a.m.w_phi = p->goal_heading_weight;
+        a.m.w_v = p->goal_speed_weight;
+    }
     for (int i = 0; i < 4; ++i) {
         a.z0[i] = p->z0[i];
         a.goal[i] = p->goal[i];

@@ -28,7 +28,9 @@ SWITCH_STATE, SWITCH_PLAN = 0, 1
 
 class nnp_vehicle_spec(C.Structure):
     _fields_ = [("z0", C.c_float * 4), ("waypoints", C.POINTER(C.c_float)),
-                ("n_waypoints", C.c_int32), ("obst", C.c_void_p), ("P", C.c_int32)]
+                ("n_waypoints", C.c_int32), ("obst", C.c_void_p), ("P", C.c_int32),
+                ("own_goal_weights", C.c_int32), ("goal_heading_weight", C.c_float),
+                ("goal_speed_weight", C.c_float)]
 
 
 class nnp_vehicle_state(C.Structure):
@@ -94,6 +96,11 @@ class Fleet:
             pts = v.get("points")
             specs[i].P = 0 if pts is None else int(pts.shape[0])
             specs[i].obst = None if pts is None or pts.shape[0] == 0 else pts.data_ptr()
+            gw = v.get("goal_weights")
+            if gw is not None:         # this vehicle's own goal heading / speed weights
+                specs[i].own_goal_weights = 1
+                specs[i].goal_heading_weight = float(np.float32(gw[0]))
+                specs[i].goal_speed_weight = float(np.float32(gw[1]))
         self.n = len(vehicles)
         self.h = C.c_void_p()
         rc = lib().nnp_fleet_create(C.byref(self.h), planner.h,

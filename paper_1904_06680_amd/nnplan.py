@@ -49,6 +49,8 @@ class nnp_problem(C.Structure):
         ("obst", C.c_void_p), ("P", C.c_int32), ("N", C.c_int32), ("T", C.c_int32),
         ("inst", C.c_uint32), ("seed", C.c_uint64), ("warm_theta", C.c_void_p),
         ("n_prop", C.c_int32), ("prop_mu", C.c_void_p), ("prop_log_sigma", C.c_void_p),
+        ("own_goal_weights", C.c_int32), ("goal_heading_weight", C.c_float),
+        ("goal_speed_weight", C.c_float),
     ]
 
 
@@ -302,6 +304,11 @@ class Planner:
             pr.prop_mu = mu.data_ptr()
             pr.prop_log_sigma = ls.data_ptr()
             pr.n_prop = int(n_prop)
+        gw = getattr(scene, "goal_weights", None)
+        if gw is not None:             # this problem's own goal heading / speed weights
+            pr.own_goal_weights = 1
+            pr.goal_heading_weight = float(np.float32(gw[0]))
+            pr.goal_speed_weight = float(np.float32(gw[1]))
         return pr, keep
 
     def plan_async(self, pr: nnp_problem, out: dict, stream=None, noalloc: bool = False):

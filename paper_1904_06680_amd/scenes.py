@@ -73,13 +73,16 @@ class Scene:
     """One planning problem: start state, goal setpoint, previous controls, obstacle points
     (float32 rows x, y, vx, vy) and the horizon."""
 
-    def __init__(self, z0, goal, points, T, a_prev=None, name=""):
+    def __init__(self, z0, goal, points, T, a_prev=None, name="", goal_weights=None):
         self.z0 = np.asarray(z0, F32).reshape(4)
         self.goal = np.asarray(goal, F32).reshape(4)
         self.points = np.ascontiguousarray(np.asarray(points, F32).reshape(-1, 4))
         self.T = int(T)
         self.a_prev = None if a_prev is None else np.asarray(a_prev, F32).reshape(2)
         self.name = name
+        # optional (heading, speed) weights of the goal terms for this problem alone; None: the
+        # planner model's
+        self.goal_weights = None if goal_weights is None else tuple(float(w) for w in goal_weights)
 
     @property
     def P(self) -> int:

@@ -28,17 +28,28 @@ from .nnplan import Planner
 from .proposal import Proposal
 
 
-def c4_vehicles(n: int, seed: int = 0, device=None):
+# The served workload's per-kind goal weights: parking plans with (2, 0.5) instead of the
+# preset's (3, 0.5), whose heading term keeps vehicles from backing into the slot (a sweep of the
+# 64-vehicle workload); waypoint missions keep the preset's.
+SERVED_GOAL_WEIGHTS = {"parking": (2.0, 0.5)}
+
+
+def c4_vehicles(n: int, seed: int = 0, device=None, goal_weights=None):
+    """n vehicles, alternating waypoint missions and parking slots. goal_weights maps a mission
+    kind ("waypoints", "parking") to that kind's own (heading, speed) goal weights; kinds it does
+    not name plan with the planner model's."""
     import torch
     vs, kinds = [], []
+    gw = goal_weights or {}
     for i in range(n):
         if i % 2 == 0:
             z0, wps = scenes.mission_waypoints(1000 * seed + i)
-            vs.append(dict(z0=z0, waypoints=wps, points=None))
+            vs.append(dict(z0=z0, waypoints=wps, points=None, goal_weights=gw.get("waypoints")))
             kinds.append("waypoints")
         else:
             z0, wps, pts = scenes.parking_slot(1000 * seed + i)
-            vs.append(dict(z0=z0, waypoints=wps, points=torch.from_numpy(pts).to(device)))
+            vs.append(dict(z0=z0, waypoints=wps, points=torch.from_numpy(pts).to(device),
+                           goal_weights=gw.get("parking")))
             kinds.append("parking")
     return vs, kinds
 
@@ -52,7 +63,8 @@ def tuned_planner(preset: dict, vehicles, T: int, n_samples: int, device: int = 
         pts = v.get("points")
         pts = np.zeros((0, 4), np.float32) if pts is None else pts.cpu().numpy()
         scs.append(scenes.Scene(np.asarray(v["z0"], np.float32),
-                                np.asarray(v["waypoints"][0], np.float32), pts, T))
+                                np.asarray(v["waypoints"][0], np.float32), pts, T,
+                                goal_weights=v.get("goal_weights")))
     res = autotune.tune_batch(preset, scs, [n_samples] * len(scs), list(range(len(scs))),
                               reps=2, device=device)
     return Planner(preset, device=device, lanes_per_sample=res["lanes_per_sample"],
@@ -111,10 +123,17 @@ def main(argv=None) -> int:
     ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
                     help="weights of the terminal heading / speed terms of the cost (default: "
                          "the served preset's 3.0 and 0.5; 0 0 gives the plain cost)")
+    ap.add_argument("--parking-terms", type=float, nargs=2,
+                    default=list(SERVED_GOAL_WEIGHTS["parking"]), metavar=("W_PHI", "W_V"),
+                    help="the parking vehicles' own goal weights (default: 2.0 0.5)")
+    ap.add_argument("--waypoint-terms", type=float, nargs=2, default=None,
+                    metavar=("W_PHI", "W_V"),
+                    help="the waypoint vehicles' own goal weights (default: the preset's)")
     ap.add_argument("--switch", choices=("plan", "state"), default="plan",
                     help="pass intermediate waypoints once the last plan reached them over its "
                          "horizon (plan, NNP_SWITCH_PLAN) or once the vehicle is within the "
                          "tolerances (state)")
+    ap.add_argument("--fleet-seed", type=int, default=0, help="seed of the vehicles' layouts")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     import torch
@@ -135,7 +154,12 @@ def main(argv=None) -> int:
         enc, th, cost = lab.label(args.labels, args.label_samples, scene_seed=1, log=log)
         ok = torch.isfinite(cost)
         learn.train(prop, enc[ok].contiguous(), th[ok].contiguous(), epochs=20, log=log)
-    vs, kinds = c4_vehicles(args.vehicles, device=pl._dev())
+    gw = {}
+    if args.parking_terms:
+        gw["parking"] = tuple(args.parking_terms)
+    if args.waypoint_terms:
+        gw["waypoints"] = tuple(args.waypoint_terms)
+    vs, kinds = c4_vehicles(args.vehicles, args.fleet_seed, device=pl._dev(), goal_weights=gw)
     tol = dict(eps_phi=4.0, eps_v=1e3) if args.position_only else None
     pl.close()                  # the labelling planner; the fleet gets the tuned launch shape
     pl = tuned_planner(preset, vs, args.T, args.uniform + args.prop)
@@ -146,6 +170,7 @@ def main(argv=None) -> int:
     res["switch_rule"] = args.switch
     res["tolerances"] = "position only" if args.position_only else "Table II"
     res["goal_terms"] = [preset["goal_heading_weight"], preset["goal_speed_weight"]]
+    res["goal_terms_per_kind"] = {k: list(v) for k, v in gw.items()}
     print(json.dumps(res), flush=True)
     if args.out:
         with open(args.out, "w") as fh:

@@ -192,3 +192,33 @@ def test_c2_workload_sampled(c1_planner):
         st = int(o["status"].item())
         assert st in (0, 1)
         assert (st == 0) == math.isfinite(o["cost"].item())
+
+
+def test_problem_goal_weights():
+    """A problem's own goal heading / speed weights plan exactly as a model that carries them
+    (the served preset is C1 with weights 3 and 0.5); in a batch, problems with their own weights
+    and with the model's equal their single plans; invalid weights are rejected."""
+    rng = np.random.default_rng([3, 0x60A1])
+    sc = scenes.scene_mixed(rng, 800, 30, name="weights")
+    model_w = Planner(scenes.C4)
+    own_w = Planner(scenes.C1)
+    sw = scenes.Scene(sc.z0, sc.goal, sc.points, sc.T, goal_weights=(3.0, 0.5))
+    a = np_out(model_w.plan(sc, 4096, seed=2))
+    b = np_out(own_w.plan(sw, 4096, seed=2))
+    assert_same(a, b, "own weights = model weights")
+    plain = np_out(own_w.plan(sc, 4096, seed=2))
+    assert plain["cost"][0] != b["cost"][0]
+    scs = [scenes.scene_mixed(rng, P, T, name=f"w{i}") for i, (P, T) in
+           enumerate([(300, 20), (0, 15), (1200, 40), (64, 8)])]
+    for i, w in enumerate([(2.0, 0.5), None, (0.0, 3.0), (5.0, 0.0)]):
+        scs[i].goal_weights = w
+    Ns, seeds = [2000, 777, 3000, 64], [11, 12, 13, 14]
+    got = own_w.plan_batch(scs, Ns, seeds)
+    for i in range(len(scs)):
+        assert_same(np_out(got[i]), np_out(own_w.plan(scs[i], Ns[i], seed=seeds[i])), ("batch", i))
+    for bad in ((-1.0, 0.5), (float("nan"), 0.0), (1.0, float("inf"))):
+        with pytest.raises(NnpError) as e:
+            own_w.plan(scenes.Scene(sc.z0, sc.goal, sc.points, sc.T, goal_weights=bad), 64)
+        assert e.value.rc == NNP_EINVAL
+    model_w.close()
+    own_w.close()

@@ -52,7 +52,7 @@ def replicate(pl, vehicles, steps, T, N, seed, proposal=None, n_prop=0):
         traj = []
         for t in range(steps):
             sc = scenes.Scene(z, v["waypoints"][0], np.zeros((0, 4), np.float32) if pts is None
-                              else pts, T, a_prev=a_prev)
+                              else pts, T, a_prev=a_prev, goal_weights=v.get("goal_weights"))
             prop = None
             if proposal is not None:
                 pr, keep = pl.problem(sc, N, seed + iv, inst=t)
@@ -97,6 +97,35 @@ def test_fleet_steps_equal_independent_plans():
             assert np.array_equal(s["a"], a), (t, i)
             assert s["cost"] == np.float32(cost) or (np.isinf(s["cost"]) and np.isinf(cost))
             assert s["steps"] == t + 1 and s["waypoint"] == 0 and not s["done"]
+    fl.close()
+    pl.close()
+
+
+def test_fleet_per_vehicle_goal_weights():
+    """Vehicles with their own goal heading / speed weights (and one with the model's): every
+    fleet step equals an independent nnp_plan whose problem carries the same weights."""
+    vs = vehicles_for_test()
+    vs[0]["goal_weights"] = (3.0, 0.5)
+    vs[2]["goal_weights"] = (1.0, 2.0)
+    T, N, seed, steps = 20, 700, 7, 3
+    pl = Planner(scenes.C1)
+    fl = Fleet(pl, dev_points(vs), T=T, n_uniform=N, seed=seed)
+    got = []
+    for t in range(steps):
+        fl.step()
+        got.append(fl.state())
+    ref = replicate(pl, vs, steps, T, N, seed)
+    plain = replicate(pl, [dict(vs[0], goal_weights=None)], 1, T, N, seed)
+    for t in range(steps):
+        for i in range(len(vs)):
+            z, a, cost = ref[i][t]
+            s = got[t][i]
+            assert np.array_equal(s["z"], z), (t, i)
+            assert np.array_equal(s["a"], a), (t, i)
+            assert s["cost"] == np.float32(cost) or (np.isinf(s["cost"]) and np.isinf(cost))
+    assert ref[0][0][2] != plain[0][0][2]       # the weights do change the cost
+    say("per-vehicle weights: first costs", [round(ref[i][0][2], 4) for i in range(len(vs))],
+        "vehicle 0 with the model's:", round(plain[0][0][2], 4))
     fl.close()
     pl.close()
 
