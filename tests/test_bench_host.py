@@ -65,3 +65,15 @@ def test_oracle_c0_plan_timing_leg():
     r = bench.oracle_c0_plan()
     assert r["kind"] == "oracle" and r["ms"] > 0 and r["cores"] >= 1
     assert abs(r["value"] - 1024 * 20 / (r["ms"] / 1e3)) <= 2e-3 * r["value"]     # ms is rounded
+
+
+def test_executed_flops_bounds():
+    """The executed work of a launch: all of the method's work when every point group is tested,
+    the controller's share alone when none is, linear in between."""
+    N, T, P, w = 65536, 50, 3000, (8, 32, 32, 2)
+    full = bench.algorithmic_flops(N, T, P, w)
+    assert bench.executed_flops(N, T, P, w, 1.0) == full
+    ctrl = bench.executed_flops(N, T, P, w, 0.0)
+    assert ctrl == float(N) * T * (bench.mlp_flops(w) + bench.FLOPS_STEP_OVERHEAD)
+    half = bench.executed_flops(N, T, P, w, 0.5)
+    assert abs(half - (full + ctrl) / 2) <= 1e-6 * full
