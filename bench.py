@@ -350,7 +350,7 @@ def bench_served(pl, prop) -> dict:
     r = serve.run(p4, vs, kinds, 200, 50, 8192, 8192, proposal=prop)
     p4.close()
     return {"workload": "64 vehicles x 200 replans, 8192 proposal + 8192 uniform samples, T=50, "
-                        "cost with terminal heading/speed terms (3, 0.5; parking 2, 0.5), "
+                        "cost with terminal heading/speed terms (2, 0.1; parking 2, 0.5), "
                         "plan-based waypoint switching",
             "latency_ms_p50": round(r["latency_ms"]["p50"], 3),
             "latency_ms_p99": round(r["latency_ms"]["p99"], 3),

@@ -43,9 +43,10 @@ C0 = dict(
 C1 = dict(C0, widths=(8, 32, 32, 2), feature_set=FEAT_EIGHT)
 
 # The served closed loop: the C1 vehicle and network with the optional terminal heading and
-# speed terms (3 m per rad, 0.5 s per m/s), because its missions prescribe a heading and a stop
-# at every waypoint; chosen by a sweep of the 64-vehicle workload (plain sampler, 200 steps).
-C4 = dict(C1, goal_heading_weight=3.0, goal_speed_weight=0.5)
+# speed terms (2 m per rad, 0.1 s per m/s), because its missions prescribe a heading and a stop
+# at every waypoint; chosen by sweeps of the 64-vehicle workload (plain sampler, 200 steps,
+# three fleet layouts).
+C4 = dict(C1, goal_heading_weight=2.0, goal_speed_weight=0.1)
 
 PRESETS = {"paper": PAPER, "c0": C0, "c1": C1, "c4": C4}
 

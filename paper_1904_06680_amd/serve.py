@@ -28,9 +28,9 @@ from .nnplan import Planner
 from .proposal import Proposal
 
 
-# The served workload's per-kind goal weights: parking plans with (2, 0.5) instead of the
-# preset's (3, 0.5), whose heading term keeps vehicles from backing into the slot (a sweep of the
-# 64-vehicle workload); waypoint missions keep the preset's.
+# The served workload's per-kind goal weights: parking plans with (2, 0.5), a stronger speed term
+# than the preset's (2, 0.1) that waypoint missions use (sweeps of the 64-vehicle workload on
+# three fleet layouts, one kind's weights at a time).
 SERVED_GOAL_WEIGHTS = {"parking": (2.0, 0.5)}
 
 
@@ -122,7 +122,7 @@ def main(argv=None) -> int:
                     help="switch waypoints on position (eps_xi, eps_eta) alone")
     ap.add_argument("--goal-terms", type=float, nargs=2, default=None, metavar=("W_PHI", "W_V"),
                     help="weights of the terminal heading / speed terms of the cost (default: "
-                         "the served preset's 3.0 and 0.5; 0 0 gives the plain cost)")
+                         "the served preset's 2.0 and 0.1; 0 0 gives the plain cost)")
     ap.add_argument("--parking-terms", type=float, nargs=2,
                     default=list(SERVED_GOAL_WEIGHTS["parking"]), metavar=("W_PHI", "W_V"),
                     help="the parking vehicles' own goal weights (default: 2.0 0.5)")

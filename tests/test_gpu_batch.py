@@ -196,13 +196,14 @@ def test_c2_workload_sampled(c1_planner):
 
 def test_problem_goal_weights():
     """A problem's own goal heading / speed weights plan exactly as a model that carries them
-    (the served preset is C1 with weights 3 and 0.5); in a batch, problems with their own weights
+    (the served preset is C1 with its goal weights); in a batch, problems with their own weights
     and with the model's equal their single plans; invalid weights are rejected."""
     rng = np.random.default_rng([3, 0x60A1])
     sc = scenes.scene_mixed(rng, 800, 30, name="weights")
     model_w = Planner(scenes.C4)
     own_w = Planner(scenes.C1)
-    sw = scenes.Scene(sc.z0, sc.goal, sc.points, sc.T, goal_weights=(3.0, 0.5))
+    sw = scenes.Scene(sc.z0, sc.goal, sc.points, sc.T, goal_weights=(
+        scenes.C4["goal_heading_weight"], scenes.C4["goal_speed_weight"]))
     a = np_out(model_w.plan(sc, 4096, seed=2))
     b = np_out(own_w.plan(sw, 4096, seed=2))
     assert_same(a, b, "own weights = model weights")

@@ -288,8 +288,9 @@ def test_fleet_plan_switching_rule():
     """NNP_SWITCH_PLAN passes an intermediate waypoint once the step's best plan comes within the
     Table II tolerances at some predicted state z_h, h = 1..T (checked in FP64 on the trajectory
     of an independent nnp_plan with the same inputs); the final waypoint still needs the
-    vehicle's own state z_{t+1}; NNP_SWITCH_STATE switches only on z_{t+1}."""
-    preset = scenes.C4
+    vehicle's own state z_{t+1}; NNP_SWITCH_STATE switches only on z_{t+1}. (Goal weights 3 and
+    0.5, with which the plan on this input reaches the first waypoint only at step 25.)"""
+    preset = dict(scenes.C1, goal_heading_weight=3.0, goal_speed_weight=0.5)
     z0 = np.zeros(4, np.float32)
     wps = np.array([[3.0, 0.0, 0.0, 0.0], [20.0, 5.0, 0.0, 0.0]], np.float32)
     vs = [dict(z0=z0, waypoints=wps, points=None), dict(z0=z0, waypoints=wps[:1], points=None)]
