@@ -186,7 +186,7 @@ int nnp_set_workspace_limit(nnp_handle *h, uint64_t bytes);
  * NNP_NOALLOC_SCRATCH_BYTES (4 MiB) that every GPU the library runs on holds until the process
  * ends; the winner's outputs are re-simulated (no per-sample records). Limit: the table of
  * (T + 1) * (P rounded up to a multiple of 64) / 2 point pairs of 16 bytes, plus 64 pairs of
- * slack, the boxes of its groups of 32 pairs, the spatial order of up to 16384 points and 256
+ * slack, the boxes of its groups of 32 pairs, the spatial order of up to 2^20 points and 256
  * bytes for the key, must fit (T = 50 allows P up to 9856); larger problems
  * return NNP_EINVAL with the sizes in nnp_last_error. The key is reset by the call itself. All
  * calls on one GPU share that GPU's array: calls that overlap on one GPU (on different streams,

@@ -55,8 +55,8 @@ constexpr int CHUNK = 64;         // pairs moved by one wavefront-wide asynchron
 // one of its samples (see group_mask). Up to SORT_MAX points are first put in spatial order
 // (order_kernel) so that the groups are compact; larger sets keep the caller's order.
 constexpr int MAX_GROUP_PAIRS = 32;
-constexpr int SORT_MAX = 16384;
-constexpr int ORDER_BLOCK = 256;
+constexpr int SORT_MAX = 1 << 20;
+constexpr int ORDER_BLOCK = 1024;
 constexpr int ORDER_GRID = 64;    // cells per axis of the spatial order
 
 struct RolloutArgs {

@@ -76,7 +76,8 @@ def test_c1_launch_shapes_identical(shape):
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_small_network_point_counts(K):
     """6-16-2 at one, two and four lanes per sample, on point counts at the edges of a group (64
-    points), of a tile (4096), of the spatial order (16384) and beyond it (caller's order)."""
+    points) and of a tile (4096) (the spatial order's limit is covered by
+    test_beyond_the_spatial_order)."""
     rng = np.random.default_rng([K, 0xC011])
     cu, al = pair(scenes.C0, lanes_per_sample=K)
     for P in (1, 63, 64, 65, 200, 4095, 4097, 16384, 16385):
@@ -84,6 +85,19 @@ def test_small_network_point_counts(K):
         say(f"cull: C0 K={K} P={P} N=2048")
         assert_same(np_out(cu.plan(sc, 2048, seed=P)), np_out(al.plan(sc, 2048, seed=P)),
                     (K, P))
+    cu.close()
+    al.close()
+
+
+def test_beyond_the_spatial_order():
+    """Point sets at the spatial order's limit (2^20 points, ordered) and just beyond it (the
+    caller's order, no displacement bound: the radius alone), both equal to the exhaustive pass."""
+    rng = np.random.default_rng(99)
+    cu, al = pair(scenes.C0, lanes_per_sample=4)
+    for P in ((1 << 20), (1 << 20) + 1):
+        sc = scenes.random_scene(rng, P, 3, box=400.0, vmax=3.0)
+        say(f"cull: C0 K=4 P={P} N=256 T=3")
+        assert_same(np_out(cu.plan(sc, 256, seed=5)), np_out(al.plan(sc, 256, seed=5)), P)
     cu.close()
     al.close()
 
@@ -156,11 +170,12 @@ def test_rollout_outputs_identical():
 
 def test_batch_identical():
     """A batch of uneven problems (no points, one point, multi-tile sets, a set beyond the spatial
-    order's limit) equals the exhaustive batch."""
+    order's limit: 2^20 + 1 points) equals the exhaustive batch."""
     rng = np.random.default_rng(11)
     shapes = [(0, 64, 20), (1, 100, 5), (3000, 2500, 50), (5000, 700, 13), (20000, 300, 6),
-              (120, 4096, 20), (2049, 97, 5)]
-    scs = [scenes.scene_mixed(rng, P, T, name=f"b{i}") for i, (P, N, T) in enumerate(shapes)]
+              ((1 << 20) + 1, 64, 2), (120, 4096, 20), (2049, 97, 5)]
+    scs = [scenes.scene_mixed(rng, P, T, name=f"b{i}") if P <= 20000 else
+           scenes.random_scene(rng, P, T, box=300.0) for i, (P, N, T) in enumerate(shapes)]
     Ns = [N for _, N, _ in shapes]
     seeds = list(range(len(shapes)))
     say(f"cull: batch of {len(shapes)} problems")
