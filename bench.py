@@ -260,6 +260,7 @@ def main() -> int:
         "best_costs_first_scenes": [round(c, 4) for c in costs[:3]],
     }
     if not args.no_extra:
+        line["points_scaling"] = bench_points_scaling(pl)
         line["batched_uneven"] = bench_batch(pl)
         prop_res, prop = bench_proposal(pl)
         line["proposal"] = prop_res
@@ -271,6 +272,42 @@ def main() -> int:
     pl.close()
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_points_scaling(pl, reps: int = 5) -> dict:
+    """The C1 plan (scene 0's recipe, N = 65536, T = 50) with 1x, 4x and 16x its obstacle points
+    in the same box: rollout kernel time with the group skipping and with every point tested
+    (all_points), and the share of groups tested."""
+    import torch
+
+    from paper_1904_06680_amd import scenes
+    from paper_1904_06680_amd.nnplan import Planner
+    full = Planner(scenes.C1, device=pl.device, all_points=True)
+    rows = []
+    for mult in (1, 4, 16):
+        sc = scenes.scene_c1(0, n_static=2000 * mult, n_dyn=20 * mult)
+        row = {"P": sc.P}
+        for name, p in (("culled", pl), ("all_points", full)):
+            pr, keep = p.problem(sc, N_SAMPLES, seed=0)
+            res = p.alloc_result(sc.T)
+            p.plan_async(pr, res)
+            torch.cuda.synchronize()
+            p.set_timing(True)
+            p.kernel_time(reset=True)
+            for _ in range(reps):
+                p.plan_async(pr, res)
+            torch.cuda.synchronize()
+            ms, n = p.kernel_time(reset=True)
+            p.set_timing(False)
+            row[f"{name}_kernel_ms"] = round(ms / max(n, 1), 4)
+            if name == "culled":
+                row["point_groups_tested"] = round(point_groups_tested(p, [(pr, keep, res)]), 4)
+            del keep
+        row["speedup"] = round(row["all_points_kernel_ms"] / row["culled_kernel_ms"], 2)
+        rows.append(row)
+    full.close()
+    return {"workload": "C1 scene 0 recipe with 1x, 4x, 16x the points (same 130 m box), "
+                        "N=65536, T=50", "rows": rows}
 
 
 def bench_batch(pl) -> dict:
