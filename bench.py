@@ -156,6 +156,14 @@ def cpu_baseline(scene, preset, target_s: float) -> dict:
                       f"{el:.1f} s"}
 
 
+_T_START = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """One progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.perf_counter() - _T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +222,7 @@ def main() -> int:
         pl.plan_async(pr, out)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t0
+    progress(f"timed region: {args.steps} plans, {elapsed / args.steps * 1e3:.3f} ms each")
     kern_ms, launches = pl.kernel_time(reset=True)
     scene_ms = per_scene_kernel_ms(pl, probs)
     pl.set_timing(False)
@@ -260,15 +269,21 @@ def main() -> int:
         "best_costs_first_scenes": [round(c, 4) for c in costs[:3]],
     }
     if not args.no_extra:
+        progress("points-scaling leg")
         line["points_scaling"] = bench_points_scaling(pl)
+        progress("batched leg")
         line["batched_uneven"] = bench_batch(pl)
+        progress("learned-proposal leg")
         prop_res, prop = bench_proposal(pl)
         line["proposal"] = prop_res
+        progress("served leg")
         line["served"] = bench_served(pl, prop)
         prop.close()
     if not args.no_cpu:
+        progress("CPU baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(scs[0], preset, args.cpu_seconds)
         line["cpu_baseline_c0"] = oracle_c0_plan()
+    progress("done")
     pl.close()
     print(json.dumps(line), flush=True)
     return 0
