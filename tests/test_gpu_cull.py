@@ -1,6 +1,7 @@
 """GPU tests of the obstacle pass's group skipping (nnp_model.all_points = 0, the default).
 
-A wavefront skips a group of 64 points at a step when the group's bounding box lies farther than
+A wavefront skips a group of points (16 or 32 consecutive pairs in spatial order, by launch
+shape) at a step when the group's bounding box lies farther than
 the cull radius (the rectangle's corner distance and, for the distance features, d_cap) from
 every one of its samples; such points cannot change a collision flag, a margin below 1 or the
 capped nearest distance. The results must therefore be the same bits as with every point tested
@@ -55,6 +56,19 @@ def test_c1_full_size_plan_identical(seed):
     cu, al = pair(scenes.C1)
     assert_same(np_out(cu.plan(sc, 65536, seed=0)), np_out(al.plan(sc, 65536, seed=0)),
                 f"c1 scene {seed}")
+    cu.close()
+    al.close()
+
+
+@pytest.mark.parametrize("mult", [4, 16])
+def test_dense_scenes_identical(mult):
+    """The benchmark scene's recipe with 4 and 16 times its points in the same box (12000 and
+    48000 points, the densities of the bench's points-scaling leg): skipping equals the
+    exhaustive pass."""
+    sc = scenes.scene_c1(0, n_static=2000 * mult, n_dyn=20 * mult)
+    say(f"cull: C1 scene 0 x{mult} points N=8192 T={sc.T} P={sc.P}")
+    cu, al = pair(scenes.C1)
+    assert_same(np_out(cu.plan(sc, 8192, seed=2)), np_out(al.plan(sc, 8192, seed=2)), mult)
     cu.close()
     al.close()
 
