@@ -870,11 +870,12 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
     // The winner's states from z0 and its recorded controls by the model step's own functions
     // (same inputs, same operations, hence the same bits as in the rollout), reordered so that
     // little stays sequential: the steering tangents and, once the heading and speed chain is
-    // known, every step's sincos are computed in parallel; the position chain comes last. Staged
-    // in LDS (T <= NNP_MAX_T).
+    // known, every step's sincos are computed in parallel; the position chain comes last, and the
+    // trajectory is written out by the whole workgroup. Staged in LDS (T <= NNP_MAX_T).
     __shared__ float2 ctl[NNP_MAX_T];
     __shared__ float tds[NNP_MAX_T];
     __shared__ float phis[NNP_MAX_T + 1], vs[NNP_MAX_T + 1], cs[NNP_MAX_T + 1], sn[NNP_MAX_T + 1];
+    __shared__ float2 xys[NNP_MAX_T + 1];
     const int T = a.T;
     for (int h = tid; h < T; h += BLOCK) {
         const float2 c = a.rec_ctrl[(size_t)h * a.N + best];
@@ -890,12 +891,31 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
         }
     }
     __syncthreads();
+    // The two chains run in one lane, CH steps at a time: a full chunk's inputs are read from LDS
+    // together before its steps, so its dependent steps wait for LDS once; the last steps (fewer
+    // than CH) go one by one.
+    constexpr int CH = 8;
+    const int TF = T / CH * CH;
     if (tid == 0) {
         float phi = a.z0[2], v = a.z0[3];
         phis[0] = phi;
         vs[0] = v;
-        for (int h = 0; h < T; ++h) {
-            heading_speed_step(a.m, ctl[h].y, tds[h], phi, v);
+        for (int h0 = 0; h0 < TF; h0 += CH) {
+            float cy[CH], td[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                cy[k] = ctl[h0 + k].y;
+                td[k] = tds[h0 + k];
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                heading_speed_step<true>(a.m, cy[k], td[k], phi, v);
+                phis[h0 + k + 1] = phi;
+                vs[h0 + k + 1] = v;
+            }
+        }
+        for (int h = TF; h < T; ++h) {
+            heading_speed_step<true>(a.m, ctl[h].y, tds[h], phi, v);
             phis[h + 1] = phi;
             vs[h + 1] = v;
         }
@@ -910,17 +930,29 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
     __syncthreads();
     if (tid == 0) {
         float x = a.z0[0], y = a.z0[1];
-        for (int h = 0; h <= T; ++h) {
-            if (o.traj) reinterpret_cast<float4 *>(o.traj)[h] = make_float4(x, y, phis[h], vs[h]);
-            if (h == T) {
-                if (o.goal_reached)
-                    o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi,
-                                                         a.m.eps_v, a.goal, x, y, phis[T], vs[T],
-                                                         cs[T], sn[T]);
-                break;
+        for (int h0 = 0; h0 < TF; h0 += CH) {
+            float td[CH], c[CH], sv[CH], vv[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                td[k] = tds[h0 + k];
+                c[k] = cs[h0 + k];
+                sv[k] = sn[h0 + k];
+                vv[k] = vs[h0 + k];
             }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                xys[h0 + k] = make_float2(x, y);
+                position_step(a.m, td[k], c[k], sv[k], vv[k], x, y);
+            }
+        }
+        for (int h = TF; h < T; ++h) {
+            xys[h] = make_float2(x, y);
             position_step(a.m, tds[h], cs[h], sn[h], vs[h], x, y);
         }
+        xys[T] = make_float2(x, y);
+        if (o.goal_reached)
+            o.goal_reached[0] = within_tolerance(a.m.eps_xi, a.m.eps_eta, a.m.eps_phi, a.m.eps_v,
+                                                 a.goal, x, y, phis[T], vs[T], cs[T], sn[T]);
         if (o.cost) o.cost[0] = key_cost;
         if (o.best_index) o.best_index[0] = best;
         if (o.status) o.status[0] = isinf(key_cost) ? NNP_INFEASIBLE : NNP_OK;
@@ -929,6 +961,10 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
         const ThetaSource src = make_source<NetT>(a, best);
         for (int k = tid; k < NetT::NTHETA; k += BLOCK) o.theta[k] = src.one(k);
     }
+    __syncthreads();
+    if (o.traj)
+        for (int h = tid; h <= T; h += BLOCK)
+            reinterpret_cast<float4 *>(o.traj)[h] = make_float4(xys[h].x, xys[h].y, phis[h], vs[h]);
 }
 
 __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,

@@ -27,6 +27,25 @@ constexpr float PI_F = 3.14159274101257324f;        // smallest float above pi
 constexpr float TWO_PI_HI = 6.28318548202514648f;   // float nearest 2 pi (above it)
 constexpr float TWO_PI_LO = -1.74845553e-7f;         // 2 pi - TWO_PI_HI
 
+// One +-2 pi correction of an angle at or beyond +-PI_F: the wrap of the heading after a step and
+// of heading errors. In the per-sample code the correction is a branch that the wavefront skips
+// when none of its lanes needs it (the usual case).
+__device__ __forceinline__ float wrap_pi(float a)
+{
+    if (a >= PI_F) a = (a - TWO_PI_HI) - TWO_PI_LO;
+    else if (a <= -PI_F) a = (a + TWO_PI_HI) + TWO_PI_LO;
+    return a;
+}
+
+// The same bits without a branch, for a chain of dependent steps in one lane: (a - k HI) - k LO
+// with k in {-1, 0, 1} is (a - HI) - LO, a itself, or (a + HI) + LO (k HI and k LO are exact,
+// and subtracting -x is adding x).
+__device__ __forceinline__ float wrap_pi_select(float a)
+{
+    const float k = (a >= PI_F ? 1.0f : 0.0f) - (a <= -PI_F ? 1.0f : 0.0f);
+    return (a - k * TWO_PI_HI) - k * TWO_PI_LO;
+}
+
 // Constants derived from nnp_model on the host (Table I, Table II and the cost weights).
 struct DevModel {
     float dt;
@@ -387,9 +406,7 @@ __device__ __forceinline__ int within_tolerance(float eps_xi, float eps_eta, flo
     const float gx = goal[0] - x, gy = goal[1] - y;
     const float xi_g = fmaf(c, gx, s * gy);
     const float eta_g = fmaf(c, gy, -(s * gx));
-    float dphi = goal[2] - phi;
-    if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
-    else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+    const float dphi = wrap_pi(goal[2] - phi);
     return fabsf(xi_g) <= eps_xi && fabsf(eta_g) <= eps_eta && fabsf(dphi) <= eps_phi &&
            fabsf(goal[3] - v) <= eps_v;
 }
@@ -401,14 +418,14 @@ __device__ __forceinline__ int within_tolerance(float eps_xi, float eps_eta, flo
 // The model step in two parts, with td = tan(delta_max a0) computed by the caller (model_step)
 // or ahead of time: heading and speed (they do not depend on the position) and the position
 // (from the old heading's c, s and the old speed).
+template <bool SELECT_WRAP = false>
 __device__ __forceinline__ void heading_speed_step(const DevModel &m, float a1, float td,
                                                    float &phi, float &v)
 {
     const float u = fmaf(a1 + 1.0f, m.u_half_range, m.u_min);
     const float ds = m.dt * v;
     float nphi = fmaf(ds * td, m.inv_L, phi);
-    if (nphi >= PI_F) nphi = (nphi - TWO_PI_HI) - TWO_PI_LO;
-    else if (nphi <= -PI_F) nphi = (nphi + TWO_PI_HI) + TWO_PI_LO;
+    nphi = SELECT_WRAP ? wrap_pi_select(nphi) : wrap_pi(nphi);
     phi = nphi;
     v = fminf(fmaxf(fmaf(m.dt, u, v), m.v_min), m.v_max);
 }
@@ -495,9 +512,7 @@ struct SampleSim {
         const float gx = goal[0] - x, gy = goal[1] - y;
         const float xi_g = fmaf(c, gx, s * gy);
         const float eta_g = fmaf(c, gy, -(s * gx));
-        float dphi = goal[2] - phi;
-        if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
-        else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+        const float dphi = wrap_pi(goal[2] - phi);
         if constexpr (NetT::FEAT == 0) {
             f[0] = xi_g * m.inv_nxi;
             f[1] = eta_g * m.inv_neta;
@@ -539,9 +554,7 @@ struct SampleSim {
         const float gx = x - goal[0], gy = y - goal[1];
         float J = sqrtf(fmaf(gx, gx, gy * gy)) + m.effort_scale * effort;
         if (m.w_phi > 0.0f) {
-            float dphi = goal[2] - phi;
-            if (dphi >= PI_F) dphi = (dphi - TWO_PI_HI) - TWO_PI_LO;
-            else if (dphi <= -PI_F) dphi = (dphi + TWO_PI_HI) + TWO_PI_LO;
+            const float dphi = wrap_pi(goal[2] - phi);
             J += m.w_phi * fabsf(dphi);
         }
         if (m.w_v > 0.0f) J += m.w_v * fabsf(goal[3] - v);
