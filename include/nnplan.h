@@ -168,8 +168,9 @@ int nnp_n_theta(const nnp_handle *h);
  * winner is re-simulated with its obstacle passes. Both give the same bits. */
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
 
-/* Largest per-sample record workspace nnp_plan may use (default 2^30 bytes); 0 makes every plan
- * re-simulate its winner instead. Results do not depend on it. Returns NNP_EINVAL for h == NULL. */
+/* Largest per-sample record workspace nnp_plan and nnp_plan_batch may use (default 2^30 bytes;
+ * a batch needs the sum over its problems); 0 makes every plan re-simulate its winner instead.
+ * Results do not depend on it. Returns NNP_EINVAL for h == NULL. */
 int nnp_set_record_limit(nnp_handle *h, uint64_t bytes);
 
 /* Cap on the device workspace the handle grows on demand (extrapolation table, per-sample
@@ -201,13 +202,17 @@ int nnp_plan_noalloc(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *h
  * problems first, so uneven sizes share the GPU without a launch per problem.
  * The call copies `count` problem descriptors to the device through a pinned staging buffer
  * owned by the handle (it waits for the previous batch's copy before reusing it) and enqueues
- * three kernels. Results are bit-identical to nnp_plan on each problem and to every lane layout.
+ * four kernels. The winners' outputs are gathered from per-sample records, one region per
+ * problem, when the batch's 8 * sum(N T) bytes fit the record limit and the workspace cap, and
+ * re-simulated otherwise. Results are bit-identical to nnp_plan on each problem and to every lane
+ * layout.
  * Returns NNP_EINVAL if count is outside 1..NNP_MAX_BATCH or any problem is invalid
  * (nnp_last_error names it).
- * HIP graph capture: the call records one host-to-device copy from the staging buffer and three
+ * HIP graph capture: the call records one host-to-device copy from the staging buffer and four
  * kernels (no memsets, no host synchronisation). The handle's batch workspace must already be
  * large enough, i.e. an uncaptured call with at least as many problems, samples-times-points and
- * table entries must come first, else NNP_EINVAL. Replays re-read the staging buffer, so between
+ * table entries must come first, else NNP_EINVAL; records are used under capture only when the
+ * allocation made before holds them (else the winners are re-simulated). Replays re-read the staging buffer, so between
  * the capture and the graph's last replay no other nnp_plan_batch call may be made on the same
  * handle (use a second handle for other batches); nnp_plan and nnp_rollout do not touch it. */
 int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_result *results,

@@ -858,9 +858,10 @@ __global__ __launch_bounds__(BLOCK) void replay_batch_kernel(const RolloutArgs *
 }
 
 // The winner's outputs from the records the rollout wrote (the same values the replay computes:
-// the records are the rollout's own states and controls, the cost is the argmin key's).
+// the records are the rollout's own states and controls, the cost is the argmin key's), by one
+// workgroup.
 template <class NetT>
-__global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, const ReplayOut o)
+__device__ __forceinline__ void gather_body(const RolloutArgs &a, const ReplayOut &o)
 {
     const int tid = threadIdx.x;
     const unsigned long long key = *a.best_key;
@@ -967,6 +968,20 @@ __global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, cons
             reinterpret_cast<float4 *>(o.traj)[h] = make_float4(xys[h].x, xys[h].y, phis[h], vs[h]);
 }
 
+template <class NetT>
+__global__ __launch_bounds__(BLOCK) void gather_kernel(const RolloutArgs a, const ReplayOut o)
+{
+    gather_body<NetT>(a, o);
+}
+
+// One workgroup per problem of a batch whose records fit.
+template <class NetT>
+__global__ __launch_bounds__(BLOCK) void gather_batch_kernel(const RolloutArgs *probs,
+                                                             const ReplayOut *outs)
+{
+    gather_body<NetT>(probs[blockIdx.x], outs[blockIdx.x]);
+}
+
 __global__ __launch_bounds__(BLOCK) void theta_kernel(PhiloxKey key, uint32_t inst, uint32_t i0,
                                                       uint32_t N, uint32_t nt,
                                                       const float *__restrict__ mu,
@@ -999,6 +1014,7 @@ struct Variant {
                                  hipStream_t);
     void (*launch_replay_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
     void (*launch_gather)(const RolloutArgs &, const ReplayOut &, hipStream_t);
+    void (*launch_gather_batch)(const RolloutArgs *, const ReplayOut *, int count, hipStream_t);
 };
 
 template <class NetT, class SH>
@@ -1048,12 +1064,20 @@ void launch_gather_t(const RolloutArgs &a, const ReplayOut &o, hipStream_t s)
     hipLaunchKernelGGL((gather_kernel<NetT>), dim3(1), dim3(BLOCK), 0, s, a, o);
 }
 
+template <class NetT>
+void launch_gather_batch_t(const RolloutArgs *probs, const ReplayOut *outs, int count,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((gather_batch_kernel<NetT>), dim3(count), dim3(BLOCK), 0, s, probs, outs);
+}
+
 #define NNP_SHAPED(NIN, H1, H2, FEAT, SH)                                                         \
     {{NIN, H1, (H2) ? (H2) : 2, (H2) ? 2 : 0}, (H2) ? 3 : 2, FEAT, SH::K, SH::RB, SH::TP, SH::GP,  \
      Net<NIN, H1, H2, FEAT>::NTHETA, launch_rollout_t<Net<NIN, H1, H2, FEAT>, SH>,                 \
      launch_replay_t<Net<NIN, H1, H2, FEAT>, SH::K>,                                               \
      launch_rollout_batch_t<Net<NIN, H1, H2, FEAT>, SH>,                                           \
-     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, SH::K>, launch_gather_t<Net<NIN, H1, H2, FEAT>>}
+     launch_replay_batch_t<Net<NIN, H1, H2, FEAT>, SH::K>,                                         \
+     launch_gather_t<Net<NIN, H1, H2, FEAT>>, launch_gather_batch_t<Net<NIN, H1, H2, FEAT>>}
 #define NNP_VARIANT(NIN, H1, H2, FEAT, K) NNP_SHAPED(NIN, H1, H2, FEAT, Shape<K>)
 
 using ShapeWideTile = Shape<8, 512, 4096>;      // one LDS buffer holds an 8192-point step
@@ -1713,6 +1737,28 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
     if (!rc) rc = grow(h, &h->d_bkeys, &h->bkeys_bytes, (size_t)count * 8, s, "batch keys");
     if (!rc) rc = grow(h, &h->d_bmeta, &h->bmeta_bytes, meta, s, "batch descriptors");
     if (rc) return rc;
+    // Records of every problem's samples, one region after another, when all fit the limits as
+    // in nnp_plan: the winners' outputs are then gathered instead of re-simulated (same bits).
+    // Under stream capture only an allocation made before is used.
+    size_t rec_need = 0;
+    bool record = true;
+    for (int i = 0; i < count && record; ++i) {
+        const size_t one = (size_t)args[i].N * (size_t)args[i].T * sizeof(float2);
+        record = one < (1ull << 31);
+        rec_need += one;
+    }
+    record = record && rec_need <= h->rec_limit &&
+             workspace_bytes(h) - h->rec_bytes + std::max(rec_need, h->rec_bytes) <= h->ws_limit &&
+             (!capturing || rec_need <= h->rec_bytes);
+    if (record) {
+        rc = grow(h, &h->d_rec, &h->rec_bytes, rec_need, s, "sample records");
+        if (rc) return rc;
+        float2 *rec = static_cast<float2 *>(h->d_rec);
+        for (int i = 0; i < count; ++i) {
+            args[i].rec_ctrl = rec;
+            rec += (size_t)args[i].N * (size_t)args[i].T;
+        }
+    }
     if (!h->meta_copied && hipEventCreateWithFlags(&h->meta_copied, hipEventDisableTiming) !=
                                hipSuccess)
         return fail(h, NNP_EDEVICE, "hipEventCreate failed");
@@ -1766,9 +1812,11 @@ int nnp_plan_batch(nnp_handle *h, const nnp_problem *probs, int count, nnp_resul
     h->var->launch_rollout_batch(d_args, d_items, n_items, h->dm.oc == 0.0f, s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "rollout_batch_kernel launch");
-    h->var->launch_replay_batch(d_args, d_outs, count, s);
+    if (record) h->var->launch_gather_batch(d_args, d_outs, count, s);
+    else h->var->launch_replay_batch(d_args, d_outs, count, s);
     e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(h, e, "replay_batch_kernel launch");
+    if (e != hipSuccess)
+        return hip_fail(h, e, record ? "gather_batch_kernel launch" : "replay_batch_kernel launch");
     h->err.clear();
     return NNP_OK;
 }

@@ -479,7 +479,8 @@ class Planner:
         _check(nnp_set_timing(self.h, enable), self.h)
 
     def set_record_limit(self, nbytes: int):
-        """Largest per-sample record workspace of plan(); 0 re-simulates every winner."""
+        """Largest per-sample record workspace of plan() and plan_batch(); 0 re-simulates every
+        winner."""
         _check(nnp_set_record_limit(self.h, nbytes), self.h)
 
     def set_workspace_limit(self, nbytes: int):

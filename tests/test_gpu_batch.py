@@ -1,8 +1,8 @@
 """GPU tests of batched planning (many independent problems in one persistent launch).
 
 Every problem of a batch must come out bit-identical to a single nnp_plan call on it (which the
-parity tests pin to the oracle), for every lane layout, and when the batch is captured into a
-HIP graph and replayed. A few small C0 problems of a batch are also checked against the oracle's
+parity tests pin to the oracle), for every lane layout, with the winners gathered from records
+or re-simulated, and when the batch is captured into a HIP graph and replayed. A few small C0 problems of a batch are also checked against the oracle's
 plan directly.
 """
 import math
@@ -77,6 +77,21 @@ def test_batch_equals_single_plans(c1_planner):
         got = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
         for i in range(len(scs)):
             assert_same(ref[i], got[i], (rep, i))
+
+
+def test_batch_records_equal_winner_replay(c1_planner):
+    """The batch's winners gathered from the per-sample records (when every problem's records
+    fit the handle's limit) and re-simulated (record limit 0) give the same outputs, bit for
+    bit."""
+    scs, Ns, seeds = mixed_batch(2)
+    say(f"batch records vs replay: C1, {len(scs)} problems")
+    c1_planner.set_record_limit(1 << 30)
+    rec = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
+    c1_planner.set_record_limit(0)
+    rep = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
+    c1_planner.set_record_limit(1 << 30)
+    for i in range(len(scs)):
+        assert_same(rec[i], rep[i], i)
 
 
 def test_batch_launch_shapes_bit_identical(c1_planner):
