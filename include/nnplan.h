@@ -168,7 +168,7 @@ int nnp_n_theta(const nnp_handle *h);
  * winner is re-simulated with its obstacle passes. Both give the same bits. */
 int nnp_plan(nnp_handle *h, const nnp_problem *p, nnp_result *r, void *hip_stream);
 
-/* Largest per-sample record workspace nnp_plan and nnp_plan_batch may use (default 2^30 bytes;
+/* Largest per-sample record workspace nnp_plan and nnp_plan_batch may use (default 2^32 bytes;
  * a batch needs the sum over its problems); 0 makes every plan re-simulate its winner instead.
  * Results do not depend on it. Returns NNP_EINVAL for h == NULL. */
 int nnp_set_record_limit(nnp_handle *h, uint64_t bytes);

@@ -1163,7 +1163,7 @@ struct nnp_handle {
     // per-sample records of nnp_plan (states and controls of every sample)
     void *d_rec = nullptr;
     size_t rec_bytes = 0;
-    uint64_t rec_limit = 1ull << 30;
+    uint64_t rec_limit = 1ull << 32;
     uint64_t ws_limit = UINT64_MAX;    // cap on the grown device workspace (all buffers above)
     // batched planning: tables, keys, descriptors (device and pinned host)
     void *d_bext = nullptr, *d_bkeys = nullptr, *d_bmeta = nullptr, *h_bmeta = nullptr;

@@ -85,11 +85,11 @@ def test_batch_records_equal_winner_replay(c1_planner):
     bit."""
     scs, Ns, seeds = mixed_batch(2)
     say(f"batch records vs replay: C1, {len(scs)} problems")
-    c1_planner.set_record_limit(1 << 30)
+    c1_planner.set_record_limit(1 << 32)
     rec = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
     c1_planner.set_record_limit(0)
     rep = [np_out(o) for o in c1_planner.plan_batch(scs, Ns, seeds)]
-    c1_planner.set_record_limit(1 << 30)
+    c1_planner.set_record_limit(1 << 32)
     for i in range(len(scs)):
         assert_same(rec[i], rep[i], i)
 

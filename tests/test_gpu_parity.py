@@ -350,11 +350,11 @@ def test_goal_heading_and_speed_cost_terms_parity(preset_name):
 # Winner outputs: gathered from the rollout's per-sample records, or re-simulated
 # --------------------------------------------------------------------------------------------
 def _plan_both_paths(pl, sc, N, **kw):
-    pl.set_record_limit(1 << 30)
+    pl.set_record_limit(1 << 32)
     rec = np_out(pl.plan(sc, N, **kw))
     pl.set_record_limit(0)
     rep = np_out(pl.plan(sc, N, **kw))
-    pl.set_record_limit(1 << 30)
+    pl.set_record_limit(1 << 32)
     return rec, rep
 
 
