@@ -279,6 +279,8 @@ def main() -> int:
         progress("served leg")
         line["served"] = bench_served(pl, prop)
         prop.close()
+        progress("paper-context leg")
+        line["paper_context"] = bench_paper_context()
     if not args.no_cpu:
         progress("CPU baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(scs[0], preset, args.cpu_seconds)
@@ -411,6 +413,56 @@ def bench_served(pl, prop) -> dict:
             "vehicles_per_kind": r["vehicles_per_kind"],
             "mean_waypoints_reached": r["mean_waypoints_reached"],
             "launch_shape": shape}
+
+
+# The paper's own figures (Table III and Sect. III): average computation time of one planning
+# step on an Intel i7-7700K with one NVIDIA Titan V, TSHC with 15 restarts of n = 20480 samples
+# over H = 200, host-GPU transfers included. Context, not a target: the sampler, the sample count
+# (taken here as 15 x 20480) and the hardware differ.
+PAPER_SAMPLES = 15 * 20480
+PAPER_FIGURES = [
+    ("Experiment 5 (parking): NN-[5,2,2], the 20 printed points", (5, 2, 2), "exp5", 0.088),
+    ("Experiment 2: NN-[5,2,2], no points, goal 50 m", (5, 2, 2), "exp2", 0.036),
+    ("Experiment 2: NN-[5,10,2], no points, goal 50 m", (5, 10, 2), "exp2", 0.047),
+    ("Experiment 2: NN-[5,10,10,2], no points, goal 50 m", (5, 10, 10, 2), "exp2", 0.130),
+]
+
+
+def bench_paper_context(reps: int = 5) -> dict:
+    """The paper preset (its vehicle, rate limit, features and networks) on the paper's workloads
+    at 15 x 20480 samples and H = 200: wall time of one plan (inputs resident on the device) and
+    rollout-steps/s, beside the paper's figure for the same experiment and network."""
+    import numpy as np
+    import torch
+
+    from paper_1904_06680_amd import scenes
+    from paper_1904_06680_amd.nnplan import Planner
+    rows = []
+    for name, widths, kind, paper_s in PAPER_FIGURES:
+        preset = dict(scenes.PAPER, widths=widths)
+        if kind == "exp5":
+            sc = scenes.scene_exp5_parking(T=200)
+        else:
+            sc = scenes.Scene([0, 0, 0, 0], [50, 0, 0, 0], np.zeros((0, 4)), 200, name="exp2")
+        pl = Planner(preset, device=0)
+        pr, keep = pl.problem(sc, PAPER_SAMPLES, seed=0)
+        res = pl.alloc_result(sc.T)
+        pl.plan_async(pr, res)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pl.plan_async(pr, res)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        del keep
+        pl.close()
+        rows.append({"workload": name, "ms_per_plan": round(ms, 3),
+                     "rollout_steps_per_s": PAPER_SAMPLES * sc.T / (ms / 1e3),
+                     "paper_ms": paper_s * 1e3})
+    return {"samples": PAPER_SAMPLES, "H": 200,
+            "paper_hardware": "Intel i7-7700K + NVIDIA Titan V, TSHC, host-GPU transfers "
+                              "included (Table III, Sect. III)",
+            "rows": rows}
 
 
 if __name__ == "__main__":

@@ -381,16 +381,10 @@ __device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x
 {
     static_assert(64 % K == 0 && K <= 16, "whole samples per wavefront");
     constexpr int R = 64 / K;      // rounds for a full segment; a partial one stops early
+    constexpr int RB = 8;          // rounds whose boxes are held in registers at once
     uint64_t need = 0;
-    // every round's box is read first (in bounds), so the reads overlap; the empty asm at the end
-    // uses them on every path, which keeps the compiler from moving a read past an early exit
-    v4f bx[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) bx[r] = boxes[r * K + q];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (r * K >= ng) break;
-        const v4f b = bx[r];
+    // One round: the K lanes of every sample test boxes r K .. r K + K - 1.
+    auto round = [&](const v4f b, int r) {
         const float ex = fmaxf(fmaxf(b.x - x, x - b.z), 0.0f);
         const float ey = fmaxf(fmaxf(b.y - y, y - b.w), 0.0f);
         const float d2 = fmaf(ex, ex, ey * ey);
@@ -398,9 +392,36 @@ __device__ __forceinline__ uint64_t group_mask(const v4f *boxes, int ng, float x
 #pragma unroll
         for (int sh = 32; sh >= K; sh >>= 1) m |= m >> sh;
         need |= (m & ((1ull << K) - 1)) << (r * K);
-    }
+    };
+    // The boxes of up to RB rounds are read first (in bounds), so the reads overlap; the empty asm
+    // at the end uses them on every path, which keeps the compiler from moving a read past an
+    // early exit. With fewer lanes per sample (more rounds) they are read RB rounds at a time,
+    // which keeps the box registers at 4 RB.
+    if constexpr (R <= RB) {
+        v4f bx[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) asm volatile("" ::"v"(bx[r].x));
+        for (int r = 0; r < R; ++r) bx[r] = boxes[r * K + q];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r * K >= ng) break;
+            round(bx[r], r);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) asm volatile("" ::"v"(bx[r].x));
+    } else {
+        for (int r0 = 0; r0 < R && r0 * K < ng; r0 += RB) {
+            v4f bx[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) bx[r] = boxes[(r0 + r) * K + q];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if ((r0 + r) * K >= ng) break;
+                round(bx[r], r0 + r);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) asm volatile("" ::"v"(bx[r].x));
+        }
+    }
     return ng >= 64 ? need : need & ((1ull << ng) - 1);
 }
 
