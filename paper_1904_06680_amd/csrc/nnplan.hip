@@ -44,7 +44,7 @@ constexpr int BLOCK = 256;
 constexpr int POINT_PAD = 64;   // points per step padded to a multiple of this (pairs per
                                 // subset then come in whole groups of four for K <= 8)
 constexpr int TILE_PAIRS = 2048;  // point pairs per LDS buffer (two buffers: 64 KiB); 1536 for
-                                  // K = 16, so that three workgroups share a CU
+                                  // K = 16, so that three workgroups share a CU, 1024 for K <= 2
 constexpr int BUFFER_RSRC_FLAGS = 0x00020000;   // buffer descriptor word 3: 32-bit data format
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
@@ -580,7 +580,9 @@ __device__ __forceinline__ void wait_copies()
 // layer receives its inputs.
 // ---------------------------------------------------------------------------------------------
 constexpr int rollout_block(int K) { return 256; }
-constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : TILE_PAIRS; }
+// One or two lanes per sample serve the small networks, whose registers allow more wavefronts
+// than two 64 KiB buffers per workgroup would: they take 1024-pair tiles (four workgroups per CU).
+constexpr int tile_pairs(int K) { return K >= 16 ? 1536 : K <= 2 ? 1024 : TILE_PAIRS; }
 #ifndef NNP_K8_GROUP_PAIRS
 #define NNP_K8_GROUP_PAIRS 16
 #endif

@@ -90,11 +90,11 @@ def test_c1_launch_shapes_identical(shape):
 @pytest.mark.parametrize("K", [1, 2, 4])
 def test_small_network_point_counts(K):
     """6-16-2 at one, two and four lanes per sample, on point counts at the edges of a group (64
-    points) and of a tile (4096) (the spatial order's limit is covered by
-    test_beyond_the_spatial_order)."""
+    points) and of a tile (2048 points at one or two lanes per sample, 4096 at four) (the spatial
+    order's limit is covered by test_beyond_the_spatial_order)."""
     rng = np.random.default_rng([K, 0xC011])
     cu, al = pair(scenes.C0, lanes_per_sample=K)
-    for P in (1, 63, 64, 65, 200, 4095, 4097, 16384, 16385):
+    for P in (1, 63, 64, 65, 200, 2047, 2049, 4095, 4097, 16384, 16385):
         sc = scenes.random_scene(rng, P, 20, box=40.0)
         say(f"cull: C0 K={K} P={P} N=2048")
         assert_same(np_out(cu.plan(sc, 2048, seed=P)), np_out(al.plan(sc, 2048, seed=P)),
