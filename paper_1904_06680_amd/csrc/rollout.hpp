@@ -37,13 +37,15 @@ __device__ __forceinline__ float wrap_pi(float a)
     return a;
 }
 
-// The same bits without a branch, for a chain of dependent steps in one lane: (a - k HI) - k LO
-// with k in {-1, 0, 1} is (a - HI) - LO, a itself, or (a + HI) + LO (k HI and k LO are exact,
-// and subtracting -x is adding x).
+// The same bits without a branch, for a chain of dependent steps in one lane: (a - s1) - s2 with
+// (s1, s2) = (HI, LO), (-HI, -LO) or (+0, +0) selected by the same tests is (a - HI) - LO,
+// (a + HI) + LO (subtracting -x is adding x), or a itself (subtracting +0 keeps a, -0 included).
 __device__ __forceinline__ float wrap_pi_select(float a)
 {
-    const float k = (a >= PI_F ? 1.0f : 0.0f) - (a <= -PI_F ? 1.0f : 0.0f);
-    return (a - k * TWO_PI_HI) - k * TWO_PI_LO;
+    const bool up = a >= PI_F, dn = a <= -PI_F;
+    const float s1 = up ? TWO_PI_HI : (dn ? -TWO_PI_HI : 0.0f);
+    const float s2 = up ? TWO_PI_LO : (dn ? -TWO_PI_LO : 0.0f);
+    return (a - s1) - s2;
 }
 
 // Constants derived from nnp_model on the host (Table I, Table II and the cost weights).

@@ -56,9 +56,14 @@ def singles(pl, scs, Ns, seeds):
     return [np_out(pl.plan(sc, N, seed=s)) for sc, N, s in zip(scs, Ns, seeds)]
 
 
+def bits(x):
+    """The array's bit patterns (floats compared bit for bit: the sign of zero included)."""
+    return x.view(np.uint32) if x.dtype == np.float32 else x
+
+
 def assert_same(a, b, where):
     for k in KEYS:
-        assert np.array_equal(a[k], b[k]), (where, k)
+        assert np.array_equal(bits(a[k]), bits(b[k])), (where, k)
 
 
 @pytest.fixture(scope="module")

@@ -38,9 +38,15 @@ def np_out(d, keys=KEYS):
     return {k: d[k].cpu().numpy() for k in keys if k in d}
 
 
+def bits(x):
+    """The array's bit patterns (floats compared bit for bit: the sign of zero and NaN payloads
+    included)."""
+    return x.view(np.uint32) if x.dtype == np.float32 else x
+
+
 def assert_same(a, b, where):
     for k in a:
-        assert np.array_equal(a[k], b[k], equal_nan=True), (where, k)
+        assert np.array_equal(bits(a[k]), bits(b[k])), (where, k)
 
 
 def pair(preset, **kw):
