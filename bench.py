@@ -334,10 +334,18 @@ def bench_batch(pl) -> dict:
     scs, Ns, seeds = scenes.batch_c2(0)
     tune = autotune.tune_batch(scenes.C1, scs, Ns, seeds, reps=3)
     steps = sum(N * sc.T for sc, N in zip(scs, Ns))
+    flops = sum(algorithmic_flops(N, sc.T, sc.P, scenes.C1["widths"]) for sc, N in zip(scs, Ns))
+    achieved = flops / (tune["ms"] / 1e3) / 1e12
     return {"workload": "256 problems, N log-uniform 4096-65536, P log-uniform 100-5000, "
                         "T in {20,40,60,80}, MLP 8-32-32-2",
             "rollout_steps": steps, "ms": round(tune["ms"], 3),
             "value": steps / (tune["ms"] / 1e3), "unit": "rollout-steps/s",
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                         "flops_per_call": flops,
+                         "note": "the method's flops (every point tested) over the whole call's "
+                                 "wall time"},
             "lanes_per_sample": tune["lanes_per_sample"],
             "block_threads": tune["block_threads"], "tile_pairs": tune["tile_pairs"],
             "timings_ms": {k: round(v, 3) for k, v in tune["timings_ms"].items()}}
